@@ -1,0 +1,152 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check a pin catches each.
+
+Every mutation is a copy of an oracle function with one slip in it: a dropped
+conjugate, a swapped relaxation, a wrong sign, a missing normalisation.  The
+oracle's pins must fail on every one of them; a mutation that survives all
+pins would show a blind spot.
+"""
+import numpy as np
+import pytest
+
+import oracle_pins as pins
+from oracle import pty_oracle as po
+from oracle import toy
+from ptysynth import make_scan
+
+
+def _obj_no_conj(y, obj, probe, pos, tau=po.DEFAULT_TAU):
+    n = probe.shape[0]
+    num = np.zeros(obj.shape, complex)
+    den = np.zeros(obj.shape)
+    for j, (p, q) in enumerate(np.asarray(pos)):
+        num[p:p + n, q:q + n] += probe * y[j]          # slip: conj dropped
+        den[p:p + n, q:q + n] += np.abs(probe) ** 2
+    out = obj.copy()
+    ok = den > tau * np.max(np.abs(probe) ** 2)
+    out[ok] = num[ok] / den[ok]
+    return out
+
+
+def _probe_no_conj(y, obj, probe, pos, tau=po.DEFAULT_TAU):
+    n = probe.shape[0]
+    num = np.zeros((n, n), complex)
+    den = np.zeros((n, n))
+    for j, (p, q) in enumerate(np.asarray(pos)):
+        o = obj[p:p + n, q:q + n]
+        num += o * y[j]                                 # slip: conj dropped
+        den += np.abs(o) ** 2
+    out = probe.copy()
+    ok = den > tau * np.max(np.abs(obj) ** 2)
+    out[ok] = num[ok] / den[ok]
+    return out
+
+
+def _probe_den_not_squared(y, obj, probe, pos, tau=po.DEFAULT_TAU):
+    n = probe.shape[0]
+    num = np.zeros((n, n), complex)
+    den = np.zeros((n, n))
+    for j, (p, q) in enumerate(np.asarray(pos)):
+        o = obj[p:p + n, q:q + n]
+        num += np.conj(o) * y[j]
+        den += np.abs(o)                                # slip: |O| instead of |O|^2
+    out = probe.copy()
+    ok = den > tau
+    out[ok] = num[ok] / den[ok]
+    return out
+
+
+def _abc_swapped(x, divide, concur, a, b, c):
+    y = po.relax(divide, b)(x)                          # slip: b and c swapped
+    w = po.relax(concur, c)(y)
+    return a * w + (1.0 - a) * x, y
+
+
+def _abc_blend_sign(x, divide, concur, a, b, c):
+    y = po.relax(divide, c)(x)
+    w = po.relax(concur, b)(y)
+    return a * w - (1.0 - a) * x, y                     # slip: sign of the blend
+
+
+def _abc_concur_first(x, divide, concur, a, b, c):
+    y = po.relax(concur, b)(x)                          # slip: concur before divide
+    w = po.relax(divide, c)(y)
+    return a * w + (1.0 - a) * x, y
+
+
+def _relax_wrong(proj, a):
+    return lambda x: a * proj(x) + (1.0 + a) * x        # slip: sign
+
+
+def _modulus_unit(x, amp):
+    f = po.dft2(x)
+    m = np.abs(f)
+    return po.idft2(np.where(m > 0, f / np.where(m > 0, m, 1), 1.0))  # slip: amplitude dropped
+
+
+def _modulus_unnormalised_inverse(x, amp):
+    f = po.dft2(x)
+    m = np.abs(f)
+    g = np.where(m > 0, amp * f / np.where(m > 0, m, 1), amp)
+    n = x.shape[-1]
+    return po.idft2(g) * n * n                          # slip: 1/N^2 missing
+
+
+def _dft_inverse_kernel(x):
+    n0, n1 = np.asarray(x).shape[-2:]
+    return np.fft.ifft2(x, axes=(-2, -1)) * n0 * n1     # slip: exp(+i...) kernel
+
+
+def _exit_conj_probe(obj, probe, pos):
+    return np.conj(probe)[None] * po.patches(obj, pos, probe.shape[0])  # slip
+
+
+def _preset_ar_wrong(name, param=0.0):
+    if name.upper() == "AR":
+        return (1.0, 2.0, 1.0)                          # slip: AR read as SF
+    return _orig_preset(name, param)
+
+
+def _preset_raar_wrong(name, param=0.0):
+    if name.upper() == "RAAR":
+        return (0.5, param, 2.0)                        # slip: b = beta, not 2 beta
+    return _orig_preset(name, param)
+
+
+_orig_preset = po.preset
+
+MUTATIONS = {
+    "object_no_conj": [("concur_object", _obj_no_conj)],
+    "probe_no_conj": [("concur_probe", _probe_no_conj)],
+    "probe_den_not_squared": [("concur_probe", _probe_den_not_squared)],
+    "abc_b_c_swapped": [("abc_iteration", _abc_swapped)],
+    "abc_blend_sign": [("abc_iteration", _abc_blend_sign)],
+    "abc_concur_first": [("abc_iteration", _abc_concur_first)],
+    "relax_sign": [("relax", _relax_wrong)],
+    "modulus_amplitude_dropped": [("modulus_projection", _modulus_unit)],
+    "modulus_inverse_unnormalised": [("modulus_projection", _modulus_unnormalised_inverse)],
+    "dft_sign": [("dft2", _dft_inverse_kernel)],
+    "exit_wave_conj_probe": [("exit_waves", _exit_conj_probe)],
+    "preset_ar": [("preset", _preset_ar_wrong)],
+    "preset_raar": [("preset", _preset_raar_wrong)],
+}
+
+
+@pytest.fixture(scope="module")
+def tiny_scan():
+    return make_scan("tiny_n32")
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(name, monkeypatch, tiny_scan):
+    for attr, fn in MUTATIONS[name]:
+        monkeypatch.setattr(po, attr, fn)
+        if hasattr(toy, attr):
+            monkeypatch.setattr(toy, attr, fn)
+    checks = list(pins.ALL_PINS) + [lambda: pins.pin_true_state_is_fixed_point(tiny_scan)]
+    caught = 0
+    for pin in checks:
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught > 0, f"mutation {name} survived every pin"
