@@ -1,0 +1,185 @@
+/*
+ * ptyabc.h -- C ABI of the MI355X (gfx950) library for the generalised 'abc'
+ * set-projection iteration of blind ptychography
+ * (Mei & Maiden, "Set projection algorithms for blind ptychographic phase
+ * retrieval").
+ *
+ * One call of pty_iterate(scan, n) runs n iterations of
+ *
+ *     x_{k+1} = a P^b_C P^c_D x_k + (1 - a) x_k                  (Introduction,
+ *                                                    the generalised formula)
+ *
+ * over the product space of exit waves x = [x_0 .. x_{J-1}], one N x N wave
+ * per scan position (the product-space construction of divide and concur),
+ * with the relaxed projection P^a_S = a P_S + (1 - a) I (Introduction).
+ *
+ *   P_D  divide: per exit wave, F^-1 [ sqrt(I_j) F x_j / |F x_j| ]; where
+ *        F x_j = 0 the phase is taken as 0.  F is the unnormalised 2-D DFT
+ *        with the zero frequency at index [0][0] (no shift).
+ *   P_C  concur: the least-squares consensus of the exit waves with one object
+ *        O (H x W) and one probe P (N x N).  The flow of the 'abc' method forms
+ *        exit waves from the current probe and object, projects, and updates
+ *        both.  Object step: O = sum_j S_j^T(conj(P) y_j) / sum_j S_j^T |P|^2;
+ *        then, when the probe is being reconstructed, probe step
+ *        P = sum_j conj(S_j O) y_j / sum_j |S_j O|^2 with the new object.
+ *        A pixel whose denominator is not above tau * max|P|^2 (object) or
+ *        tau * max|O|^2 (probe) keeps its previous value.  Both sums are
+ *        accumulated in float64 in a fixed order, so results are
+ *        bit-reproducible.  P_C y is z_j = P S_j O.
+ *
+ * Data layout (all row-major, complex = interleaved (re, im) float32):
+ *   object  [H][W] complex      probe [N][N] complex
+ *   exit waves x, y [J][N][N] complex      intensities [J][N][N] float32
+ *   positions [J][2] int32: (row, col) of the top-left corner of patch j,
+ *             0 <= row <= H - N, 0 <= col <= W - N.
+ *
+ * Errors: every call returns a pty_status; no exception crosses the ABI.  An
+ * invalid argument leaves the scan unchanged.  After PTY_ERR_DEVICE a scan
+ * accepts only pty_destroy_scan.  pty_last_error() gives a thread-local
+ * message for the last failing call on this thread.
+ *
+ * Concurrency: a scan must not be used from two threads at once; distinct
+ * scans may be.  pty_iterate is asynchronous on the scan's stream; getters
+ * synchronise that stream.
+ */
+#ifndef PTYABC_H
+#define PTYABC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pty_scan pty_scan; /* opaque; created and destroyed by the library */
+
+typedef enum {
+  PTY_OK = 0,
+  PTY_ERR_INVALID_ARG = 1,   /* bad pointer, size, value or range            */
+  PTY_ERR_OUT_OF_MEMORY = 2, /* workspace too small                          */
+  PTY_ERR_DEVICE = 3,        /* a HIP call failed; the scan is now unusable  */
+  PTY_ERR_BAD_STATE = 4,     /* call not valid in the scan's current state   */
+  PTY_ERR_DIVERGED = 5,      /* a metric of the last iteration is not finite */
+  PTY_ERR_UNSUPPORTED = 6    /* valid request this build does not implement  */
+} pty_status;
+
+typedef enum {
+  PTY_STORE_FP32 = 0, /* exit waves x, y kept as complex float32              */
+  PTY_STORE_FP16 = 1  /* kept as complex float16 times a power-of-two scale;
+                         transforms and projections still run in float32 and
+                         the overlap sums in float64                          */
+} pty_storage;
+
+/* Named algorithms (Introduction lists them; the paper gives (1,1,1) for
+ * divide and concur).  (a, b, c) used for each:
+ *   DC (1,1,1)   AR (1,1,2)   DR (1/2,2,2)   SF (1,2,1)
+ *   RAAR(beta) (1/2, 2 beta, 2)   RRR(beta) (beta/2, 2, 2)
+ *   T_lambda (1/(1+lambda), 1+lambda, 1+lambda)                              */
+typedef enum {
+  PTY_DC = 0, PTY_AR = 1, PTY_DR = 2, PTY_SF = 3,
+  PTY_RAAR = 4, PTY_RRR = 5, PTY_TLAMBDA = 6
+} pty_algorithm;
+
+typedef struct {
+  int32_t n;                  /* N: 32, 64, 128 or 256                          */
+  int32_t n_pos;              /* J >= 1                                          */
+  int32_t obj_h, obj_w;       /* H, W >= N                                       */
+  const int32_t *pos;         /* [J][2] (row, col), see above                    */
+  const float *intensity;     /* [J][N][N], finite and >= 0, unshifted          */
+  const float *init_object;   /* [H][W] complex                                  */
+  const float *init_probe;    /* [N][N] complex                                  */
+  int32_t inputs_on_device;   /* 0: the four arrays are host memory, 1: device   */
+  int32_t storage;            /* pty_storage                                     */
+  int32_t blind;              /* 0: probe known (never updated), 1: updated      */
+  int32_t probe_update_start; /* blind: probe updated from this iteration on     */
+  int32_t full_metrics;       /* 1: compute all three metrics every iteration
+                                 (forces x and y to be kept even where (a,b,c)
+                                 would not need them); 0: only those whose
+                                 inputs are read anyway (others are NaN)       */
+  int32_t metric_capacity;    /* entries of the metric history ring; 0: 4096    */
+  double tau;                 /* division guard; 0 selects 1e-10                 */
+} pty_scan_desc;
+
+/* Metrics of one iteration k (from x_k):
+ *   fourier_err     sum (|F x_k| - sqrt(I))^2 / sum I
+ *   consistency_err sum |z - y|^2 / sum |y|^2,  y = P^c_D x_k, z = P_C y
+ *   change          ||x_{k+1} - x_k|| / ||x_k||                              */
+typedef struct {
+  int64_t iteration;
+  double fourier_err;
+  double consistency_err;
+  double change;
+} pty_metrics;
+
+/* Exact device-workspace size for desc, in bytes; 0 if desc is invalid. */
+size_t pty_workspace_bytes(const pty_scan_desc *desc);
+
+/* Create a scan.  d_workspace: device memory of at least
+ * pty_workspace_bytes(desc) bytes, 256-byte aligned, owned by the caller, kept
+ * alive and unmoved until pty_destroy_scan.  stream: a hipStream_t (NULL: the
+ * default stream) on which all of the scan's work is queued.  The input arrays
+ * are copied; the caller may free them on return.  The first iteration starts
+ * from x_0 = P_0 S_j O_0 (the flow's first step). */
+pty_status pty_create_scan(const pty_scan_desc *desc, void *d_workspace, size_t ws_bytes,
+                           void *stream, pty_scan **out);
+
+/* Select (a, b, c) for subsequent iterations.  All three must be finite and a
+ * must be nonzero; any other values (under- or over-relaxation) are allowed. */
+pty_status pty_set_algorithm(pty_scan *scan, double a, double b, double c);
+
+/* Select a named algorithm; param is beta (RAAR, RRR) or lambda (T_lambda)
+ * and is ignored otherwise. */
+pty_status pty_set_algorithm_named(pty_scan *scan, int32_t algorithm, double param);
+
+/* Queue n >= 0 iterations on the scan's stream and return. */
+pty_status pty_iterate(pty_scan *scan, int32_t n);
+
+/* Queue n iterations of each of count scans.  The scans' kernels are launched
+ * interleaved, iteration by iteration, so that scans on different streams
+ * overlap on the device.  Each scan's result is identical to pty_iterate on
+ * it alone. */
+pty_status pty_iterate_many(pty_scan *const *scans, int32_t count, int32_t n);
+
+/* Wait for all queued work of the scan. */
+pty_status pty_synchronize(pty_scan *scan);
+
+/* Copy the current object ([H][W] complex, 2*H*W floats) or probe
+ * ([N][N] complex, 2*N*N floats) into dst (host or device memory).
+ * n_floats is dst's capacity in floats. */
+pty_status pty_get_object(pty_scan *scan, float *dst, size_t n_floats, int32_t dst_on_device);
+pty_status pty_get_probe(pty_scan *scan, float *dst, size_t n_floats, int32_t dst_on_device);
+
+/* Metrics of the last completed iteration.  PTY_ERR_BAD_STATE before the
+ * first iteration; PTY_ERR_DIVERGED (with *out filled) if one is not finite. */
+pty_status pty_get_metrics(pty_scan *scan, pty_metrics *out);
+
+/* Up to cap most recent entries, oldest first; *n_out receives the count. */
+pty_status pty_get_metric_history(pty_scan *scan, pty_metrics *dst, int32_t cap, int32_t *n_out);
+
+/* Number of completed iterations. */
+int64_t pty_get_iteration(const pty_scan *scan);
+
+/* Read the state: x = x_k (the iterate the next iteration starts from),
+ * y = P^c_D x_{k-1} of the last iteration, object, probe.  Each pointer may be
+ * NULL to skip it; sizes are those of the layout above (complex float32,
+ * also under FP16 storage). */
+pty_status pty_get_state(pty_scan *scan, float *x, float *y, float *obj, float *probe,
+                         int32_t on_device);
+
+/* Replace the state (checkpoint restore, parity tests).  x must be given; y
+ * may be NULL (then it is zeroed); obj and probe may be NULL to keep the
+ * current ones.  The iteration counter is left unchanged. */
+pty_status pty_set_state(pty_scan *scan, const float *x, const float *y, const float *obj,
+                         const float *probe, int32_t on_device);
+
+/* Release the scan (not the caller's workspace).  NULL is a no-op. */
+void pty_destroy_scan(pty_scan *scan);
+
+const char *pty_status_string(int32_t status);
+const char *pty_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTYABC_H */

@@ -1,0 +1,720 @@
+// Host engine and C ABI: argument validation, workspace layout, the per-scan
+// state machine (pending update, metric bookkeeping) and the launch sequence
+// of one iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ptyabc.h"
+#include "params.hpp"
+
+using namespace pty;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pty_status fail(pty_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kTileW = 64, kTileH = 16;
+constexpr int kDefaultCap = 4096;
+constexpr double kDefaultTau = 1e-10;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// exit-wave state of the next divide prologue
+enum Mode { MODE_INIT = 0, MODE_MATERIAL = 1, MODE_PENDING = 2 };
+
+struct Layout {
+  size_t amp, x, y, tmp, obj, probe, pos, tile_off, tile_list, part, met, ring, tile_max, pmax, tw, flag, total;
+  int tiles_x, tiles_y, n_tiles, max_list, G, chunk, npb, nslot, cap;
+  size_t elem_bytes;
+};
+
+bool desc_shape_ok(const pty_scan_desc* d, std::string* why) {
+  if (!d) { *why = "desc is NULL"; return false; }
+  if (!divide_supported(d->n)) { *why = "n must be 32, 64, 128 or 256"; return false; }
+  if (d->n_pos < 1) { *why = "n_pos must be >= 1"; return false; }
+  if (d->obj_h < d->n || d->obj_w < d->n) { *why = "object must be at least N x N"; return false; }
+  if (int64_t(d->obj_h) * d->obj_w > (int64_t(1) << 31)) { *why = "object too large"; return false; }
+  if (d->storage != PTY_STORE_FP32 && d->storage != PTY_STORE_FP16) { *why = "storage must be 0 or 1"; return false; }
+  if (d->blind != 0 && d->blind != 1) { *why = "blind must be 0 or 1"; return false; }
+  if (d->probe_update_start < 0) { *why = "probe_update_start must be >= 0"; return false; }
+  if (d->full_metrics != 0 && d->full_metrics != 1) { *why = "full_metrics must be 0 or 1"; return false; }
+  if (d->metric_capacity < 0) { *why = "metric_capacity must be >= 0"; return false; }
+  if (!(d->tau >= 0.0) || !std::isfinite(d->tau)) { *why = "tau must be finite and >= 0"; return false; }
+  if (d->inputs_on_device != 0 && d->inputs_on_device != 1) { *why = "inputs_on_device must be 0 or 1"; return false; }
+  return true;
+}
+
+Layout make_layout(const pty_scan_desc* d) {
+  Layout L{};
+  const size_t N = size_t(d->n), J = size_t(d->n_pos), H = size_t(d->obj_h), W = size_t(d->obj_w);
+  const size_t nn = N * N;
+  L.elem_bytes = d->storage == PTY_STORE_FP16 ? 4 : 8;
+  L.tiles_x = int((W + kTileW - 1) / kTileW);
+  L.tiles_y = int((H + kTileH - 1) / kTileH);
+  L.n_tiles = L.tiles_x * L.tiles_y;
+  // a window of N pixels meets at most ceil((N-1)/T)+1 tiles along an axis
+  const int per_pos = ((d->n + kTileH - 2) / kTileH + 1) * ((d->n + kTileW - 2) / kTileW + 1);
+  L.max_list = int(J) * per_pos;
+  L.npb = int((nn + 255) / 256);
+  int G = std::max(1, (2048 + L.npb - 1) / L.npb);
+  G = std::min<int>(G, int(J));
+  L.chunk = int((J + G - 1) / G);
+  L.G = int((J + L.chunk - 1) / L.chunk);
+  L.nslot = divide_slots(d->n);
+  L.cap = d->metric_capacity > 0 ? d->metric_capacity : kDefaultCap;
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += align_up(bytes); return o; };
+  L.amp = take(J * nn * 4);
+  L.x = take(J * nn * L.elem_bytes);
+  L.y = take(J * nn * L.elem_bytes);
+  L.tmp = (d->n == 256 && d->storage == PTY_STORE_FP16) ? take(J * nn * 8) : size_t(-1);
+  L.obj = take(H * W * 8);
+  L.probe = take(nn * 8);
+  L.pos = take(J * 8);
+  L.tile_off = take((size_t(L.n_tiles) + 1) * 4);
+  L.tile_list = take(size_t(L.max_list) * 4);
+  L.part = take(3 * size_t(L.G) * nn * 8);
+  L.met = take(J * size_t(L.nslot) * MF_COUNT * 8);
+  L.ring = take(size_t(L.cap) * kRingFields * 8);
+  L.tile_max = take(size_t(L.n_tiles) * 4);
+  L.pmax = take(size_t(L.npb) * 4);
+  L.tw = take(N * 8);
+  L.flag = take(64);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct pty_scan {
+  int N = 0, J = 0, H = 0, W = 0;
+  int fp16 = 0, blind = 0, probe_update_start = 0, full_metrics = 1;
+  double tau = kDefaultTau;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* ws = nullptr;
+  Layout L{};
+  float scale = 1.0f, inv_scale = 1.0f;
+  double a = 1.0, b = 1.0, c = 1.0;
+  int64_t k = 0;
+  int mode = MODE_INIT;
+  float pa = 1.0f, pb = 0.0f, pg = 0.0f;  // pending prologue coefficients
+  bool x_valid = false, y_valid = false;
+  bool prev_metrics_done = true;          // metrics of iteration k-1 already finalised
+  bool failed = false;
+
+  template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  float2* tmp_ptr() const { return L.tmp == size_t(-1) ? at<float2>(L.y) : at<float2>(L.tmp); }
+};
+
+namespace {
+
+pty_status device_fail(pty_scan* s, hipError_t e, const char* what) {
+  if (s) s->failed = true;
+  return fail(PTY_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define PTY_HIP(s, call, what)                          \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return device_fail(s, e_, what); \
+  } while (0)
+
+pty_status check_usable(const pty_scan* s) {
+  if (!s) return fail(PTY_ERR_INVALID_ARG, "scan is NULL");
+  if (s->failed) return fail(PTY_ERR_BAD_STATE, "scan had a device error; only pty_destroy_scan is allowed");
+  return PTY_OK;
+}
+
+FinalParams final_params(const pty_scan* s) {
+  FinalParams f{};
+  f.part = s->at<double>(s->L.part);
+  f.probe = s->at<float2>(s->L.probe);
+  f.pmax_part = s->at<float>(s->L.pmax);
+  f.tile_max = s->at<float>(s->L.tile_max);
+  f.n_tiles = s->L.n_tiles;
+  f.N = s->N;
+  f.G = s->L.G;
+  f.npb = s->L.npb;
+  f.tau = s->tau;
+  f.met = s->at<double>(s->L.met);
+  f.J = s->J;
+  f.nslot = s->L.nslot;
+  f.ring = s->at<double>(s->L.ring);
+  f.cap = s->L.cap;
+  f.k_cur = -1;
+  f.k_prev = -1;
+  return f;
+}
+
+// One iteration: divide (with the pending update), object, [probe], finalise.
+pty_status launch_iteration(pty_scan* s) {
+  const hipStream_t st = s->stream;
+  DivideParams p{};
+  p.obj = s->at<float2>(s->L.obj);
+  p.probe = s->at<float2>(s->L.probe);
+  p.pos = s->at<int2>(s->L.pos);
+  p.amp = s->at<float>(s->L.amp);
+  p.tw = s->at<float2>(s->L.tw);
+  p.x = s->ws + s->L.x;
+  p.y = s->ws + s->L.y;
+  p.tmp = s->tmp_ptr();
+  p.obj_w = s->W;
+  p.j_begin = 0;
+  float al = 1.f, be = 0.f, ga = 0.f;
+  if (s->mode == MODE_MATERIAL) { al = 0.f; be = 0.f; ga = 1.f; }
+  if (s->mode == MODE_PENDING) { al = s->pa; be = s->pb; ga = s->pg; }
+  p.alpha = al; p.beta = be; p.gamma = ga;
+  const bool pending = s->mode == MODE_PENDING;
+  const bool need_y = pending && be != 0.f;
+  const bool need_x = (pending && ga != 0.f) || s->mode == MODE_MATERIAL;
+  const bool want_prev = pending && !s->prev_metrics_done;
+  p.prev_ec = want_prev && s->y_valid && (need_y || s->full_metrics);
+  p.prev_dx = want_prev && s->x_valid && (need_x || s->full_metrics);
+  p.read_y = need_y || p.prev_ec;
+  p.read_x = need_x || p.prev_dx;
+  const bool write_x = (1.0 - s->a) != 0.0 || s->full_metrics;
+  p.write_x = write_x;
+  p.c = float(s->c);
+  p.scale = s->scale;
+  p.inv_scale = s->inv_scale;
+  p.met = s->at<double>(s->L.met);
+  p.nslot = s->L.nslot;
+  PTY_HIP(s, launch_divide(s->N, s->fp16, p, s->J, st), "divide launch");
+
+  ObjParams o{};
+  o.y = s->ws + s->L.y;
+  o.inv_scale = s->inv_scale;
+  o.probe = p.probe;
+  o.pos = p.pos;
+  o.tile_off = s->at<int>(s->L.tile_off);
+  o.tile_list = s->at<int>(s->L.tile_list);
+  o.obj = s->at<float2>(s->L.obj);
+  o.H = s->H; o.W = s->W; o.N = s->N;
+  o.tiles_x = s->L.tiles_x;
+  o.n_tiles = s->L.n_tiles;
+  o.tile_max = s->at<float>(s->L.tile_max);
+  o.pmax_part = s->at<float>(s->L.pmax);
+  o.npb = s->L.npb;
+  o.tau = s->tau;
+  PTY_HIP(s, launch_object_update(s->fp16, o, st), "object launch");
+
+  const bool update_probe = s->blind && s->k >= s->probe_update_start;
+  if (update_probe) {
+    ProbeParams q{};
+    q.y = o.y;
+    q.inv_scale = s->inv_scale;
+    q.obj = o.obj;
+    q.pos = p.pos;
+    q.N = s->N; q.W = s->W; q.J = s->J;
+    q.chunk = s->L.chunk;
+    q.G = s->L.G;
+    q.part = s->at<double>(s->L.part);
+    PTY_HIP(s, launch_probe_partial(s->fp16, q, st), "probe launch");
+  }
+  FinalParams f = final_params(s);
+  f.k_cur = s->k;
+  f.k_prev = (p.prev_ec || p.prev_dx) ? s->k - 1 : -1;
+  f.ec_ok = p.prev_ec;
+  f.dx_ok = p.prev_dx;
+  PTY_HIP(s, launch_probe_final(f, update_probe, st), "finalise launch");
+
+  // the new state is pending with this iteration's (a, b)
+  s->mode = MODE_PENDING;
+  s->pa = float(s->a * s->b);
+  s->pb = float(s->a * (1.0 - s->b));
+  s->pg = float(1.0 - s->a);
+  s->x_valid = write_x;
+  s->y_valid = true;
+  s->prev_metrics_done = false;
+  s->k += 1;
+  return PTY_OK;
+}
+
+// Finalise the metrics of iteration k-1 and/or materialise x_k.
+pty_status flush(pty_scan* s, bool materialise) {
+  const bool pending = s->mode == MODE_PENDING;
+  const bool want_metrics = pending && !s->prev_metrics_done;
+  if (!want_metrics && !(materialise && s->mode != MODE_MATERIAL)) return PTY_OK;
+  FlushParams fp{};
+  fp.obj = s->at<float2>(s->L.obj);
+  fp.probe = s->at<float2>(s->L.probe);
+  fp.pos = s->at<int2>(s->L.pos);
+  fp.x = s->ws + s->L.x;
+  fp.y = s->ws + s->L.y;
+  fp.N = s->N;
+  fp.obj_w = s->W;
+  if (s->mode == MODE_INIT) { fp.alpha = 1.f; fp.beta = 0.f; fp.gamma = 0.f; }
+  else if (s->mode == MODE_MATERIAL) { fp.alpha = 0.f; fp.beta = 0.f; fp.gamma = 1.f; }
+  else { fp.alpha = s->pa; fp.beta = s->pb; fp.gamma = s->pg; }
+  fp.read_x = (s->x_valid && (fp.gamma != 0.f || want_metrics)) ? 1 : 0;
+  fp.read_y = (s->y_valid && (fp.beta != 0.f || want_metrics)) ? 1 : 0;
+  fp.scale = s->scale;
+  fp.inv_scale = s->inv_scale;
+  fp.write_x = materialise && s->mode != MODE_MATERIAL;
+  fp.met = s->at<double>(s->L.met);
+  fp.nslot = s->L.nslot;
+  PTY_HIP(s, launch_flush(s->fp16, fp, s->J, s->stream), "flush launch");
+  if (want_metrics) {
+    FinalParams f = final_params(s);
+    f.k_prev = s->k - 1;
+    f.ec_ok = fp.read_y;
+    f.dx_ok = fp.read_x;
+    PTY_HIP(s, launch_metrics_only_final(f, s->stream), "metrics launch");
+    s->prev_metrics_done = true;
+  }
+  if (fp.write_x) {
+    s->mode = MODE_MATERIAL;
+    s->x_valid = true;
+  }
+  return PTY_OK;
+}
+
+pty_status refresh_probe_max(pty_scan* s) {
+  PTY_HIP(s, launch_max_abs2_parts(s->at<float2>(s->L.probe), size_t(s->N) * s->N, s->at<float>(s->L.pmax),
+                                   s->L.npb, s->stream),
+          "probe max");
+  return PTY_OK;
+}
+
+hipMemcpyKind kind(int src_dev, int dst_dev) {
+  if (src_dev && dst_dev) return hipMemcpyDeviceToDevice;
+  if (src_dev) return hipMemcpyDeviceToHost;
+  if (dst_dev) return hipMemcpyHostToDevice;
+  return hipMemcpyHostToHost;
+}
+
+// copy an exit-wave stack between the library's storage and float32 complex
+pty_status copy_waves_out(pty_scan* s, size_t off, float* dst, int on_device) {
+  const size_t count = size_t(s->J) * s->N * s->N;
+  if (!s->fp16) {
+    PTY_HIP(s, hipMemcpyAsync(dst, s->ws + off, count * 8, kind(1, on_device), s->stream), "copy out");
+    return PTY_OK;
+  }
+  if (on_device) {
+    PTY_HIP(s, launch_convert_state(1, 0, nullptr, nullptr, s->ws + off, reinterpret_cast<float2*>(dst), count,
+                                    s->scale, s->inv_scale, s->stream),
+            "convert out");
+    return PTY_OK;
+  }
+  std::vector<_Float16> h(count * 2);
+  PTY_HIP(s, hipMemcpyAsync(h.data(), s->ws + off, count * 4, hipMemcpyDeviceToHost, s->stream), "copy out");
+  PTY_HIP(s, hipStreamSynchronize(s->stream), "sync");
+  for (size_t i = 0; i < count * 2; ++i) dst[i] = float(h[i]) * s->inv_scale;
+  return PTY_OK;
+}
+
+pty_status copy_waves_in(pty_scan* s, size_t off, const float* src, int on_device) {
+  const size_t count = size_t(s->J) * s->N * s->N;
+  if (!s->fp16) {
+    PTY_HIP(s, hipMemcpyAsync(s->ws + off, src, count * 8, kind(on_device, 1), s->stream), "copy in");
+    return PTY_OK;
+  }
+  if (on_device) {
+    PTY_HIP(s, launch_convert_state(1, 1, reinterpret_cast<const float2*>(src), s->ws + off, nullptr, nullptr, count,
+                                    s->scale, s->inv_scale, s->stream),
+            "convert in");
+    return PTY_OK;
+  }
+  std::vector<_Float16> h(count * 2);
+  for (size_t i = 0; i < count * 2; ++i) h[i] = _Float16(src[i] * s->scale);
+  PTY_HIP(s, hipMemcpyAsync(s->ws + off, h.data(), count * 4, hipMemcpyHostToDevice, s->stream), "copy in");
+  PTY_HIP(s, hipStreamSynchronize(s->stream), "sync");
+  return PTY_OK;
+}
+
+bool finite_abc(double a, double b, double c) { return std::isfinite(a) && std::isfinite(b) && std::isfinite(c); }
+
+pty_status named_abc(int32_t algo, double prm, double* a, double* b, double* c) {
+  switch (algo) {
+    case PTY_DC: *a = 1; *b = 1; *c = 1; return PTY_OK;
+    case PTY_AR: *a = 1; *b = 1; *c = 2; return PTY_OK;
+    case PTY_DR: *a = 0.5; *b = 2; *c = 2; return PTY_OK;
+    case PTY_SF: *a = 1; *b = 2; *c = 1; return PTY_OK;
+    case PTY_RAAR: *a = 0.5; *b = 2 * prm; *c = 2; return PTY_OK;
+    case PTY_RRR: *a = prm / 2; *b = 2; *c = 2; return PTY_OK;
+    case PTY_TLAMBDA: *a = 1 / (1 + prm); *b = 1 + prm; *c = 1 + prm; return PTY_OK;
+    default: return fail(PTY_ERR_INVALID_ARG, "unknown algorithm");
+  }
+}
+
+pty_status create_impl(const pty_scan_desc* d, void* d_ws, size_t ws_bytes, void* stream, pty_scan** out) {
+  if (!out) return fail(PTY_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!desc_shape_ok(d, &why)) return fail(PTY_ERR_INVALID_ARG, why);
+  if (!d->pos || !d->intensity || !d->init_object || !d->init_probe)
+    return fail(PTY_ERR_INVALID_ARG, "pos, intensity, init_object and init_probe must be non-NULL");
+  if (!d_ws) return fail(PTY_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign != 0) return fail(PTY_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  const Layout L = make_layout(d);
+  if (ws_bytes < L.total)
+    return fail(PTY_ERR_OUT_OF_MEMORY, "workspace too small: need " + std::to_string(L.total) + " bytes");
+
+  const int N = d->n, J = d->n_pos, H = d->obj_h, W = d->obj_w;
+  // positions: validate on the host
+  std::vector<int32_t> pos(size_t(J) * 2);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (d->inputs_on_device) {
+    hipError_t e = hipMemcpyAsync(pos.data(), d->pos, pos.size() * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_fail(nullptr, e, "reading positions");
+  } else {
+    std::memcpy(pos.data(), d->pos, pos.size() * 4);
+  }
+  for (int j = 0; j < J; ++j) {
+    const int r = pos[2 * j], c = pos[2 * j + 1];
+    if (r < 0 || c < 0 || r > H - N || c > W - N)
+      return fail(PTY_ERR_INVALID_ARG, "position " + std::to_string(j) + " puts the window outside the object");
+  }
+  // tile lists (ascending j)
+  std::vector<int> cnt(size_t(L.n_tiles) + 1, 0);
+  for (int j = 0; j < J; ++j) {
+    const int r = pos[2 * j], c = pos[2 * j + 1];
+    for (int ty = r / kTileH; ty <= (r + N - 1) / kTileH; ++ty)
+      for (int tx = c / kTileW; tx <= (c + N - 1) / kTileW; ++tx) cnt[size_t(ty) * L.tiles_x + tx + 1]++;
+  }
+  for (int t = 0; t < L.n_tiles; ++t) cnt[t + 1] += cnt[t];
+  std::vector<int> list(std::max(1, cnt[L.n_tiles]));
+  std::vector<int> fillp(cnt.begin(), cnt.end() - 1);
+  for (int j = 0; j < J; ++j) {
+    const int r = pos[2 * j], c = pos[2 * j + 1];
+    for (int ty = r / kTileH; ty <= (r + N - 1) / kTileH; ++ty)
+      for (int tx = c / kTileW; tx <= (c + N - 1) / kTileW; ++tx) list[fillp[size_t(ty) * L.tiles_x + tx]++] = j;
+  }
+  if (cnt[L.n_tiles] > L.max_list) return fail(PTY_ERR_INVALID_ARG, "internal: tile list bound exceeded");
+
+  pty_scan* s = new (std::nothrow) pty_scan();
+  if (!s) return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  s->N = N; s->J = J; s->H = H; s->W = W;
+  s->fp16 = d->storage == PTY_STORE_FP16;
+  s->blind = d->blind;
+  s->probe_update_start = d->probe_update_start;
+  s->full_metrics = d->full_metrics;
+  s->tau = d->tau > 0 ? d->tau : kDefaultTau;
+  s->stream = st;
+  s->ws = reinterpret_cast<char*>(d_ws);
+  s->L = L;
+  if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
+
+  auto bail = [&](pty_status r) { delete s; return r; };
+  const size_t nn = size_t(N) * N;
+  const int dev = d->inputs_on_device;
+#define CK(call, what)                                               \
+  do {                                                               \
+    hipError_t e_ = (call);                                          \
+    if (e_ != hipSuccess) return bail(device_fail(nullptr, e_, what)); \
+  } while (0)
+  CK(hipMemsetAsync(s->ws, 0, L.total, st), "clear workspace");
+  CK(hipMemcpyAsync(s->ws + L.pos, pos.data(), pos.size() * 4, hipMemcpyHostToDevice, st), "positions");
+  CK(hipMemcpyAsync(s->ws + L.tile_off, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice, st), "tile offsets");
+  CK(hipMemcpyAsync(s->ws + L.tile_list, list.data(), size_t(cnt[L.n_tiles]) * 4, hipMemcpyHostToDevice, st),
+     "tile lists");
+  std::vector<float2> tw(N);
+  for (int m = 0; m < N; ++m) {
+    const double ang = -2.0 * 3.14159265358979323846 * double(m) / double(N);
+    tw[m] = make_float2(float(std::cos(ang)), float(std::sin(ang)));
+  }
+  CK(hipMemcpyAsync(s->ws + L.tw, tw.data(), size_t(N) * 8, hipMemcpyHostToDevice, st), "twiddles");
+  CK(hipMemcpyAsync(s->ws + L.obj, d->init_object, size_t(H) * W * 8, kind(dev, 1), st), "object");
+  CK(hipMemcpyAsync(s->ws + L.probe, d->init_probe, nn * 8, kind(dev, 1), st), "probe");
+  // intensities: stage host data in the x buffer (at least 4 bytes per value)
+  const float* isrc = d->intensity;
+  if (!dev) {
+    CK(hipMemcpyAsync(s->ws + L.x, d->intensity, size_t(J) * nn * 4, hipMemcpyHostToDevice, st), "intensity");
+    isrc = s->at<float>(L.x);
+  }
+  int* bad = s->at<int>(L.flag);
+  CK(launch_amp_prepare(N, isrc, s->at<float>(L.amp), J, bad, st), "amplitudes");
+  CK(hipMemsetAsync(s->ws + L.x, 0, size_t(J) * nn * L.elem_bytes, st), "clear x");
+  CK(launch_max_abs2_parts(s->at<float2>(L.probe), nn, s->at<float>(L.pmax), L.npb, st), "probe max");
+  // float16 scale: max |x| = max|P| max|O| brought to about 2^8
+  // object maxima go to the tile-max buffer, one part per tile at most
+  const int onp = std::min(256, L.n_tiles);
+  std::vector<float> omax(onp), pmax(L.npb);
+  CK(launch_max_abs2_parts(s->at<float2>(L.obj), size_t(H) * W, s->at<float>(L.tile_max), onp, st), "object max");
+  int nbad = 0;
+  CK(hipMemcpyAsync(&nbad, bad, 4, hipMemcpyDeviceToHost, st), "flag");
+  CK(hipMemcpyAsync(omax.data(), s->ws + L.tile_max, size_t(onp) * 4, hipMemcpyDeviceToHost, st), "object max");
+  CK(hipMemcpyAsync(pmax.data(), s->ws + L.pmax, size_t(L.npb) * 4, hipMemcpyDeviceToHost, st), "probe max");
+  CK(hipStreamSynchronize(st), "create");
+#undef CK
+  if (nbad > 0) return bail(fail(PTY_ERR_INVALID_ARG, "intensity has negative or non-finite values"));
+  const double om = std::sqrt(double(*std::max_element(omax.begin(), omax.end())));
+  const double pm = std::sqrt(double(*std::max_element(pmax.begin(), pmax.end())));
+  if (!std::isfinite(om) || !std::isfinite(pm)) return bail(fail(PTY_ERR_INVALID_ARG, "object or probe not finite"));
+  if (s->fp16) {
+    const double xm = om * pm;
+    int e = 0;
+    if (xm > 0) e = 8 - int(std::ceil(std::log2(xm)));
+    e = std::max(-100, std::min(100, e));
+    s->scale = float(std::ldexp(1.0, e));
+    s->inv_scale = float(std::ldexp(1.0, -e));
+  }
+  s->mode = MODE_INIT;
+  *out = s;
+  return PTY_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t pty_workspace_bytes(const pty_scan_desc* desc) {
+  try {
+    std::string why;
+    if (!desc_shape_ok(desc, &why)) {
+      g_last_error = why;
+      return 0;
+    }
+    return make_layout(desc).total;
+  } catch (...) {
+    return 0;
+  }
+}
+
+pty_status pty_create_scan(const pty_scan_desc* desc, void* d_workspace, size_t ws_bytes, void* stream,
+                           pty_scan** out) {
+  try {
+    return create_impl(desc, d_workspace, ws_bytes, stream, out);
+  } catch (const std::exception& e) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, e.what());
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unknown error in pty_create_scan");
+  }
+}
+
+pty_status pty_set_algorithm(pty_scan* scan, double a, double b, double c) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (!finite_abc(a, b, c)) return fail(PTY_ERR_INVALID_ARG, "a, b, c must be finite");
+  if (a == 0.0) return fail(PTY_ERR_INVALID_ARG, "a must be nonzero");
+  scan->a = a;
+  scan->b = b;
+  scan->c = c;
+  return PTY_OK;
+}
+
+pty_status pty_set_algorithm_named(pty_scan* scan, int32_t algorithm, double param) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (!std::isfinite(param)) return fail(PTY_ERR_INVALID_ARG, "param must be finite");
+  double a, b, c;
+  st = named_abc(algorithm, param, &a, &b, &c);
+  if (st != PTY_OK) return st;
+  return pty_set_algorithm(scan, a, b, c);
+}
+
+pty_status pty_iterate(pty_scan* scan, int32_t n) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (n < 0) return fail(PTY_ERR_INVALID_ARG, "n must be >= 0");
+  try {
+    for (int32_t i = 0; i < n; ++i) {
+      st = launch_iteration(scan);
+      if (st != PTY_OK) return st;
+    }
+  } catch (...) {
+    scan->failed = true;
+    return fail(PTY_ERR_DEVICE, "exception during iterate");
+  }
+  return PTY_OK;
+}
+
+pty_status pty_iterate_many(pty_scan* const* scans, int32_t count, int32_t n) {
+  if (count < 0 || (count > 0 && !scans)) return fail(PTY_ERR_INVALID_ARG, "bad scans/count");
+  if (n < 0) return fail(PTY_ERR_INVALID_ARG, "n must be >= 0");
+  for (int32_t i = 0; i < count; ++i) {
+    pty_status st = check_usable(scans[i]);
+    if (st != PTY_OK) return st;
+    for (int32_t q = 0; q < i; ++q)
+      if (scans[q] == scans[i]) return fail(PTY_ERR_INVALID_ARG, "a scan is listed twice");
+  }
+  try {
+    for (int32_t it = 0; it < n; ++it) {
+      for (int32_t i = 0; i < count; ++i) {
+        pty_status st = launch_iteration(scans[i]);
+        if (st != PTY_OK) return st;
+      }
+    }
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "exception during iterate_many");
+  }
+  return PTY_OK;
+}
+
+pty_status pty_synchronize(pty_scan* scan) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
+  return PTY_OK;
+}
+
+static pty_status get_array(pty_scan* scan, size_t off, size_t floats, float* dst, size_t n_floats, int on_dev) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (!dst) return fail(PTY_ERR_INVALID_ARG, "dst is NULL");
+  if (n_floats < floats) return fail(PTY_ERR_INVALID_ARG, "dst too small: need " + std::to_string(floats) + " floats");
+  PTY_HIP(scan, hipMemcpyAsync(dst, scan->ws + off, floats * 4, kind(1, on_dev ? 1 : 0), scan->stream), "copy");
+  PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
+  return PTY_OK;
+}
+
+pty_status pty_get_object(pty_scan* scan, float* dst, size_t n_floats, int32_t dst_on_device) {
+  if (!scan) return fail(PTY_ERR_INVALID_ARG, "scan is NULL");
+  return get_array(scan, scan->L.obj, size_t(scan->H) * scan->W * 2, dst, n_floats, dst_on_device);
+}
+
+pty_status pty_get_probe(pty_scan* scan, float* dst, size_t n_floats, int32_t dst_on_device) {
+  if (!scan) return fail(PTY_ERR_INVALID_ARG, "scan is NULL");
+  return get_array(scan, scan->L.probe, size_t(scan->N) * scan->N * 2, dst, n_floats, dst_on_device);
+}
+
+static pty_status read_ring(pty_scan* scan, std::vector<double>& ring) {
+  ring.resize(size_t(scan->L.cap) * kRingFields);
+  PTY_HIP(scan, hipMemcpyAsync(ring.data(), scan->ws + scan->L.ring, ring.size() * 8, hipMemcpyDeviceToHost,
+                               scan->stream),
+          "metrics copy");
+  PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
+  return PTY_OK;
+}
+
+pty_status pty_get_metrics(pty_scan* scan, pty_metrics* out) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (!out) return fail(PTY_ERR_INVALID_ARG, "out is NULL");
+  if (scan->k == 0) return fail(PTY_ERR_BAD_STATE, "no iteration has run");
+  st = flush(scan, false);
+  if (st != PTY_OK) return st;
+  std::vector<double> ring;
+  st = read_ring(scan, ring);
+  if (st != PTY_OK) return st;
+  const int64_t k = scan->k - 1;
+  const double* e = ring.data() + (k % scan->L.cap) * kRingFields;
+  out->iteration = k;
+  out->fourier_err = e[1];
+  out->consistency_err = e[2];
+  out->change = e[3];
+  if (!std::isfinite(e[1]) || (scan->full_metrics && (!std::isfinite(e[2]) || !std::isfinite(e[3]))))
+    return fail(PTY_ERR_DIVERGED, "a metric of the last iteration is not finite");
+  return PTY_OK;
+}
+
+pty_status pty_get_metric_history(pty_scan* scan, pty_metrics* dst, int32_t cap, int32_t* n_out) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (!n_out || (cap > 0 && !dst) || cap < 0) return fail(PTY_ERR_INVALID_ARG, "bad dst/cap/n_out");
+  st = flush(scan, false);
+  if (st != PTY_OK) return st;
+  std::vector<double> ring;
+  st = read_ring(scan, ring);
+  if (st != PTY_OK) return st;
+  const int64_t avail = std::min<int64_t>(scan->k, scan->L.cap);
+  const int64_t n = std::min<int64_t>(avail, cap);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t k = scan->k - n + i;
+    const double* e = ring.data() + (k % scan->L.cap) * kRingFields;
+    dst[i].iteration = k;
+    dst[i].fourier_err = e[1];
+    dst[i].consistency_err = e[2];
+    dst[i].change = e[3];
+  }
+  *n_out = int32_t(n);
+  return PTY_OK;
+}
+
+int64_t pty_get_iteration(const pty_scan* scan) { return scan ? scan->k : -1; }
+
+pty_status pty_get_state(pty_scan* scan, float* x, float* y, float* obj, float* probe, int32_t on_device) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (on_device != 0 && on_device != 1) return fail(PTY_ERR_INVALID_ARG, "on_device must be 0 or 1");
+  if (x) {
+    st = flush(scan, true);
+    if (st != PTY_OK) return st;
+    st = copy_waves_out(scan, scan->L.x, x, on_device);
+    if (st != PTY_OK) return st;
+  }
+  if (y) {
+    st = copy_waves_out(scan, scan->L.y, y, on_device);
+    if (st != PTY_OK) return st;
+  }
+  if (obj) PTY_HIP(scan, hipMemcpyAsync(obj, scan->ws + scan->L.obj, size_t(scan->H) * scan->W * 8,
+                                        kind(1, on_device), scan->stream), "copy object");
+  if (probe) PTY_HIP(scan, hipMemcpyAsync(probe, scan->ws + scan->L.probe, size_t(scan->N) * scan->N * 8,
+                                          kind(1, on_device), scan->stream), "copy probe");
+  PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
+  return PTY_OK;
+}
+
+pty_status pty_set_state(pty_scan* scan, const float* x, const float* y, const float* obj, const float* probe,
+                         int32_t on_device) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (!x) return fail(PTY_ERR_INVALID_ARG, "x must be given");
+  if (on_device != 0 && on_device != 1) return fail(PTY_ERR_INVALID_ARG, "on_device must be 0 or 1");
+  st = copy_waves_in(scan, scan->L.x, x, on_device);
+  if (st != PTY_OK) return st;
+  if (y) {
+    st = copy_waves_in(scan, scan->L.y, y, on_device);
+    if (st != PTY_OK) return st;
+  } else {
+    PTY_HIP(scan, hipMemsetAsync(scan->ws + scan->L.y, 0, size_t(scan->J) * scan->N * scan->N * scan->L.elem_bytes,
+                                 scan->stream), "clear y");
+  }
+  if (obj) PTY_HIP(scan, hipMemcpyAsync(scan->ws + scan->L.obj, obj, size_t(scan->H) * scan->W * 8,
+                                        kind(on_device, 1), scan->stream), "copy object");
+  if (probe) {
+    PTY_HIP(scan, hipMemcpyAsync(scan->ws + scan->L.probe, probe, size_t(scan->N) * scan->N * 8,
+                                 kind(on_device, 1), scan->stream), "copy probe");
+    st = refresh_probe_max(scan);
+    if (st != PTY_OK) return st;
+  }
+  PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
+  scan->mode = MODE_MATERIAL;
+  scan->x_valid = true;
+  scan->y_valid = y != nullptr;
+  scan->prev_metrics_done = true;
+  return PTY_OK;
+}
+
+void pty_destroy_scan(pty_scan* scan) {
+  if (!scan) return;
+  if (!scan->failed) (void)hipStreamSynchronize(scan->stream);
+  delete scan;
+}
+
+const char* pty_status_string(int32_t status) {
+  switch (status) {
+    case PTY_OK: return "ok";
+    case PTY_ERR_INVALID_ARG: return "invalid argument";
+    case PTY_ERR_OUT_OF_MEMORY: return "out of memory";
+    case PTY_ERR_DEVICE: return "device error";
+    case PTY_ERR_BAD_STATE: return "bad state";
+    case PTY_ERR_DIVERGED: return "diverged";
+    case PTY_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* pty_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

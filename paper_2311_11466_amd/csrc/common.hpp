@@ -1,0 +1,223 @@
+// Device building blocks shared by the gfx950 kernels: complex arithmetic,
+// compile-time DFT twiddles, fully unrolled in-register DFTs and the exit-wave
+// storage formats.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include <utility>
+
+namespace pty {
+
+// ---------------------------------------------------------------------------
+// complex float helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// Products are written with explicit fused multiply-adds so every kernel that
+// forms the same product (e.g. an exit wave P * O) rounds it identically,
+// whatever contraction the compiler would otherwise choose.
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
+}
+__device__ __forceinline__ float cnorm(float2 a) { return a.x * a.x + a.y * a.y; }
+
+// ---------------------------------------------------------------------------
+// compile-time cos / sin of 2*pi*k/L, from the Taylor series on [0, pi/2) and
+// quadrant symmetry (exact 0 and +-1 on the axes)
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double taylor_sin(double x) {
+  double term = x, sum = x;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / double((2 * n) * (2 * n + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / double((2 * n - 1) * (2 * n));
+    sum += term;
+  }
+  return sum;
+}
+// returns cos(2 pi k / L) (want_sin = false) or sin(2 pi k / L)
+constexpr double trig2pi(long k, long L, bool want_sin) {
+  k = ((k % L) + L) % L;
+  const long q = (4 * k) / L;            // quadrant
+  const long r = 4 * k - q * L;          // remainder, angle = pi/2 * r / L
+  const double t = 0.5 * kPi * double(r) / double(L);
+  const double c = (r == 0) ? 1.0 : taylor_cos(t);
+  const double s = (r == 0) ? 0.0 : taylor_sin(t);
+  double cc = 0, ss = 0;
+  switch (q) {
+    case 0: cc = c; ss = s; break;
+    case 1: cc = -s; ss = c; break;
+    case 2: cc = -c; ss = -s; break;
+    default: cc = s; ss = -c; break;
+  }
+  return want_sin ? ss : cc;
+}
+
+// d * exp(-2 pi i K / L) (forward) or d * exp(+2 pi i K / L) (inverse), with the
+// trivial angles special-cased at compile time.
+template <int L, int K, bool INV>
+__device__ __forceinline__ float2 twiddle_const(float2 d) {
+  constexpr int k = ((K % L) + L) % L;
+  if constexpr (k == 0) {
+    return d;
+  } else if constexpr (2 * k == L) {
+    return make_float2(-d.x, -d.y);
+  } else if constexpr (4 * k == L) {
+    // forward: * (-i); inverse: * (+i)
+    return INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+  } else if constexpr (4 * k == 3 * L) {
+    return INV ? make_float2(d.y, -d.x) : make_float2(-d.y, d.x);
+  } else {
+    constexpr float c = float(trig2pi(k, L, false));
+    constexpr float s = float(trig2pi(k, L, true));
+    // W = c - i s (forward), c + i s (inverse)
+    if constexpr (!INV) return make_float2(d.x * c + d.y * s, d.y * c - d.x * s);
+    else return make_float2(d.x * c - d.y * s, d.y * c + d.x * s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// compile-time loops
+// ---------------------------------------------------------------------------
+template <int B, int E, int S = 1, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + S, E, S>(std::forward<F>(f));
+  }
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int bitrev(int v, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// In-register DFT of M = 2^m points held at v[OFF + STRIDE * i], i < M.
+// Radix-2 decimation in frequency, then a compile-time relabelling so that on
+// return v[OFF + STRIDE * k] holds the k-th frequency (natural order).
+// Forward: X_k = sum_n x_n exp(-2 pi i n k / M); inverse: exp(+...), unscaled.
+// ---------------------------------------------------------------------------
+template <int M, bool INV, int STRIDE = 1, int OFF = 0, int NV>
+__device__ __forceinline__ void dft_reg(float2 (&v)[NV]) {
+  static_assert((M & (M - 1)) == 0, "power of two");
+  if constexpr (M == 1) {
+    return;
+  } else {
+    static_for<0, ilog2(M)>([&](auto st) {
+      constexpr int half = M >> (st.value + 1);
+      constexpr int span = 2 * half;
+      static_for<0, M, span>([&](auto blk) {
+        static_for<0, half>([&](auto i) {
+          constexpr int ia = OFF + STRIDE * (blk.value + i.value);
+          constexpr int ib = OFF + STRIDE * (blk.value + i.value + half);
+          const float2 a = v[ia];
+          const float2 b = v[ib];
+          v[ia] = cadd(a, b);
+          v[ib] = twiddle_const<span, i.value, INV>(csub(a, b));
+        });
+      });
+    });
+    // output of DIF is in bit-reversed order: relabel
+    float2 t[M];
+    static_for<0, M>([&](auto k) { t[k.value] = v[OFF + STRIDE * bitrev(k.value, ilog2(M))]; });
+    static_for<0, M>([&](auto k) { v[OFF + STRIDE * k.value] = t[k.value]; });
+  }
+}
+
+// 4 x 4 two-dimensional DFT on v[OFF + 4*r + c] (r: slow axis, c: fast axis).
+template <bool INV, int OFF, int NV>
+__device__ __forceinline__ void dft4x4_reg(float2 (&v)[NV]) {
+  static_for<0, 4>([&](auto r) { dft_reg<4, INV, 1, OFF + 4 * r.value>(v); });
+  static_for<0, 4>([&](auto c) { dft_reg<4, INV, 4, OFF + c.value>(v); });
+}
+
+// ---------------------------------------------------------------------------
+// exit-wave storage formats
+// ---------------------------------------------------------------------------
+struct StoreF32 {
+  using elem = float2;
+  static constexpr int kFormat = 0;
+  __device__ __forceinline__ static float2 load(const elem* p, size_t i, float /*inv_scale*/) { return p[i]; }
+  __device__ __forceinline__ static void store(elem* p, size_t i, float2 v, float /*scale*/) { p[i] = v; }
+};
+
+// complex float16 times a power-of-two scale (round to nearest even)
+struct StoreF16 {
+  using elem = __half2;
+  static constexpr int kFormat = 1;
+  __device__ __forceinline__ static float2 load(const elem* p, size_t i, float inv_scale) {
+    const float2 f = __half22float2(p[i]);
+    return make_float2(f.x * inv_scale, f.y * inv_scale);
+  }
+  __device__ __forceinline__ static void store(elem* p, size_t i, float2 v, float scale) {
+    p[i] = __float22half2_rn(make_float2(v.x * scale, v.y * scale));
+  }
+};
+
+// ---------------------------------------------------------------------------
+// block-wide float64 sum of NV values per thread, in a fixed order
+// (wave butterfly, then waves in ascending order).  red must hold
+// NV * (blockDim / 64) doubles.  All threads receive the sums.
+// ---------------------------------------------------------------------------
+template <int NV, int NT>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
+  static_assert(NT % 64 == 0, "whole waves");
+  constexpr int NW = NT / 64;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[q * NW + wave] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[q * NW + w];
+    v[q] = s;
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ float block_max(float v, float* red) {
+  constexpr int NW = NT / 64;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  float m = red[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) m = fmaxf(m, red[w]);
+  __syncthreads();
+  return m;
+}
+
+}  // namespace pty

@@ -1,0 +1,255 @@
+// Concur step P_C: deterministic overlap consensus in float64.
+//
+//   object  O(r) = sum_j [S_j^T conj(P) y_j](r) / sum_j [S_j^T |P|^2](r)
+//   probe   P(u) = sum_j conj(S_j O)(u) y_j(u) / sum_j |S_j O(u)|^2    (blind)
+//
+// Object: the object is cut into 64 x 16 tiles; each tile has the ascending
+// list of scan positions whose window meets it (built on the host).  One
+// work-group owns one tile, one thread a column of four pixels, and sums over
+// its list in list order: every exit-wave pixel is read exactly once, no
+// atomics, and the result does not depend on launch order.
+// Probe: a grid of (256-pixel block) x (position chunk) writes float64
+// partial sums; a second kernel adds the chunks in ascending order.
+#include "common.hpp"
+#include "params.hpp"
+
+namespace pty {
+
+constexpr int kTileW = 64;
+constexpr int kTileH = 16;
+
+template <class St>
+__global__ __launch_bounds__(256) void object_update_kernel(ObjParams p) {
+  __shared__ float red[4];
+  const int tile = blockIdx.x;
+  const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = tx * kTileW + lane;
+  const int row0 = ty * kTileH + wave;
+  const int N = p.N;
+  using elem = typename St::elem;
+  const elem* ys = reinterpret_cast<const elem*>(p.y);
+
+  float pm = 0.0f;
+  for (int i = threadIdx.x; i < p.npb; i += 256) pm = fmaxf(pm, p.pmax_part[i]);
+  pm = block_max<256>(pm, red);
+  const double thr = p.tau * double(pm);
+
+  double nr[4] = {0, 0, 0, 0}, ni[4] = {0, 0, 0, 0}, dd[4] = {0, 0, 0, 0};
+  const int e0 = p.tile_off[tile], e1 = p.tile_off[tile + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int j = p.tile_list[e];
+    const int2 pj = p.pos[j];
+    const int u1 = col - pj.y;
+    if ((unsigned)u1 >= (unsigned)N) continue;
+    const size_t base = size_t(j) * N * N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int u0 = row0 + 4 * i - pj.x;
+      if ((unsigned)u0 < (unsigned)N) {
+        const int u = u0 * N + u1;
+        const float2 pv = p.probe[u];
+        const float2 yv = St::load(ys, base + u, p.inv_scale);
+        const double px = pv.x, py = pv.y, yx = yv.x, yy = yv.y;
+        nr[i] += px * yx + py * yy;
+        ni[i] += px * yy - py * yx;
+        dd[i] += px * px + py * py;
+      }
+    }
+  }
+  float m = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = row0 + 4 * i;
+    if (row < p.H && col < p.W) {
+      const size_t idx = size_t(row) * p.W + col;
+      float2 o = p.obj[idx];
+      if (dd[i] > thr) {
+        o = make_float2(float(nr[i] / dd[i]), float(ni[i] / dd[i]));
+        p.obj[idx] = o;
+      }
+      m = fmaxf(m, cnorm(o));
+    }
+  }
+  m = block_max<256>(m, red);
+  if (threadIdx.x == 0) p.tile_max[tile] = m;
+}
+
+template <class St>
+__global__ __launch_bounds__(256) void probe_partial_kernel(ProbeParams p) {
+  const int N = p.N;
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  const int g = blockIdx.y;
+  const int j0 = g * p.chunk;
+  const int j1 = min(p.J, j0 + p.chunk);
+  const int u0 = u / N, u1 = u % N;
+  using elem = typename St::elem;
+  const elem* ys = reinterpret_cast<const elem*>(p.y);
+  double nr = 0.0, ni = 0.0, dd = 0.0;
+  if (u < N * N) {
+    int j = j0;
+    // four positions per step so that eight loads are in flight per thread
+    for (; j + 4 <= j1; j += 4) {
+      float2 ov[4], yv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int2 pj = p.pos[j + q];
+        ov[q] = p.obj[size_t(pj.x + u0) * p.W + (pj.y + u1)];
+        yv[q] = St::load(ys, size_t(j + q) * N * N + u, p.inv_scale);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double ox = ov[q].x, oy = ov[q].y, yx = yv[q].x, yy = yv[q].y;
+        nr += ox * yx + oy * yy;
+        ni += ox * yy - oy * yx;
+        dd += ox * ox + oy * oy;
+      }
+    }
+    for (; j < j1; ++j) {
+      const int2 pj = p.pos[j];
+      const float2 ov = p.obj[size_t(pj.x + u0) * p.W + (pj.y + u1)];
+      const float2 yv = St::load(ys, size_t(j) * N * N + u, p.inv_scale);
+      const double ox = ov.x, oy = ov.y, yx = yv.x, yy = yv.y;
+      nr += ox * yx + oy * yy;
+      ni += ox * yy - oy * yx;
+      dd += ox * ox + oy * oy;
+    }
+    const size_t plane = size_t(p.G) * N * N;
+    const size_t o = size_t(g) * N * N + u;
+    p.part[o] = nr;
+    p.part[plane + o] = ni;
+    p.part[2 * plane + o] = dd;
+  }
+}
+
+// fixed-order metric reduction over [J][nslot][MF_COUNT]; one block
+__device__ void finalize_metrics(const FinalParams& p, double* red) {
+  double acc[MF_COUNT];
+#pragma unroll
+  for (int q = 0; q < MF_COUNT; ++q) acc[q] = 0.0;
+  const int total = p.J * p.nslot;
+  for (int i = threadIdx.x; i < total; i += 256) {
+#pragma unroll
+    for (int q = 0; q < MF_COUNT; ++q) acc[q] += p.met[size_t(i) * MF_COUNT + q];
+  }
+  block_sum<MF_COUNT, 256>(acc, red);
+  if (threadIdx.x == 0) {
+    const double nan = __builtin_nan("");
+    if (p.k_cur >= 0) {
+      double* e = p.ring + (p.k_cur % p.cap) * kRingFields;
+      e[0] = double(p.k_cur);
+      e[1] = acc[MF_EF_DEN] > 0 ? acc[MF_EF_NUM] / acc[MF_EF_DEN] : nan;
+      e[2] = nan;
+      e[3] = nan;
+    }
+    if (p.k_prev >= 0) {
+      double* e = p.ring + (p.k_prev % p.cap) * kRingFields;
+      e[2] = (p.ec_ok && acc[MF_EC_DEN] > 0) ? acc[MF_EC_NUM] / acc[MF_EC_DEN] : nan;
+      e[3] = (p.dx_ok && acc[MF_DX_DEN] > 0) ? sqrt(acc[MF_DX_NUM] / acc[MF_DX_DEN]) : nan;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void probe_final_kernel(FinalParams p) {
+  __shared__ double dred[MF_COUNT * 4];
+  __shared__ float fred[4];
+  const int b = blockIdx.x + p.first_block;
+  if (b == p.npb) {
+    finalize_metrics(p, dred);
+    return;
+  }
+  const int NN = p.N * p.N;
+  const int u = b * 256 + threadIdx.x;
+  float om = 0.0f;
+  for (int i = threadIdx.x; i < p.n_tiles; i += 256) om = fmaxf(om, p.tile_max[i]);
+  om = block_max<256>(om, fred);
+  const double thr = p.tau * double(om);
+  float m = 0.0f;
+  if (u < NN) {
+    const size_t plane = size_t(p.G) * NN;
+    double nr = 0.0, ni = 0.0, dd = 0.0;
+    for (int g = 0; g < p.G; ++g) {
+      const size_t o = size_t(g) * NN + u;
+      nr += p.part[o];
+      ni += p.part[plane + o];
+      dd += p.part[2 * plane + o];
+    }
+    float2 pv = p.probe[u];
+    if (dd > thr) {
+      pv = make_float2(float(nr / dd), float(ni / dd));
+      p.probe[u] = pv;
+    }
+    m = cnorm(pv);
+  }
+  m = block_max<256>(m, fred);
+  if (threadIdx.x == 0) p.pmax_part[b] = m;
+}
+
+__global__ __launch_bounds__(256) void max_abs2_parts_kernel(const float2* a, size_t count, float* parts) {
+  __shared__ float red[4];
+  float m = 0.0f;
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < count; i += size_t(gridDim.x) * 256) {
+    m = fmaxf(m, cnorm(a[i]));
+  }
+  m = block_max<256>(m, red);
+  if (threadIdx.x == 0) parts[blockIdx.x] = m;
+}
+
+template <class St>
+__global__ void convert_kernel(int to_store, const float2* src, typename St::elem* dst_store,
+                               const typename St::elem* src_store, float2* dst, size_t count, float scale,
+                               float inv_scale) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < count; i += size_t(gridDim.x) * blockDim.x) {
+    if (to_store) St::store(dst_store, i, src[i], scale);
+    else dst[i] = St::load(src_store, i, inv_scale);
+  }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_object_update(int fp16, const ObjParams& p, hipStream_t s) {
+  if (fp16) hipLaunchKernelGGL(object_update_kernel<StoreF16>, dim3(p.n_tiles), dim3(256), 0, s, p);
+  else hipLaunchKernelGGL(object_update_kernel<StoreF32>, dim3(p.n_tiles), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_partial(int fp16, const ProbeParams& p, hipStream_t s) {
+  const dim3 grid((p.N * p.N + 255) / 256, p.G);
+  if (fp16) hipLaunchKernelGGL(probe_partial_kernel<StoreF16>, grid, dim3(256), 0, s, p);
+  else hipLaunchKernelGGL(probe_partial_kernel<StoreF32>, grid, dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_final(const FinalParams& p, int update_probe, hipStream_t s) {
+  FinalParams q = p;
+  q.first_block = update_probe ? 0 : p.npb;
+  const int blocks = update_probe ? p.npb + 1 : 1;
+  hipLaunchKernelGGL(probe_final_kernel, dim3(blocks), dim3(256), 0, s, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_metrics_only_final(const FinalParams& p, hipStream_t s) {
+  return launch_probe_final(p, 0, s);
+}
+
+hipError_t launch_max_abs2_parts(const float2* a, size_t count, float* parts, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(max_abs2_parts_kernel, dim3(nparts), dim3(256), 0, s, a, count, parts);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_state(int fp16, int to_store, const float2* src, void* dst_store, const void* src_store,
+                                float2* dst, size_t count, float scale, float inv_scale, hipStream_t s) {
+  const int blocks = int(std::min<size_t>((count + 255) / 256, 16384));
+  if (blocks <= 0) return hipSuccess;
+  if (fp16) {
+    hipLaunchKernelGGL(convert_kernel<StoreF16>, dim3(blocks), dim3(256), 0, s, to_store, src,
+                       reinterpret_cast<__half2*>(dst_store), reinterpret_cast<const __half2*>(src_store), dst,
+                       count, scale, inv_scale);
+  } else {
+    hipLaunchKernelGGL(convert_kernel<StoreF32>, dim3(blocks), dim3(256), 0, s, to_store, src,
+                       reinterpret_cast<float2*>(dst_store), reinterpret_cast<const float2*>(src_store), dst,
+                       count, scale, inv_scale);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pty

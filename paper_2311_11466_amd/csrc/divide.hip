@@ -1,0 +1,478 @@
+// Divide step P^c_D of the generalised iteration, fused with the pending
+// update of the previous iteration (see the formula in the header).
+//
+// For N <= 128 one work-group owns one diffraction pattern end to end:
+//   prologue   x_k = alpha P S_j O + beta y_{k-1} + gamma x_{k-1}   (registers)
+//   forward    2-D DFT of x_k  (three register stages, two LDS exchanges)
+//   Fourier    y^ = (c A / |X| + 1 - c) X / N^2   -- the relaxed modulus
+//              projection; since F is linear, c P_D x + (1 - c) x is formed
+//              on the spectrum and needs no copy of x_k
+//   inverse    2-D inverse DFT (mirror of the forward, two exchanges)
+//   epilogue   store y_k
+//
+// The 2-D DFT of N = 4 M points per axis is split, for both axes, as
+//   r = r2 + M r1,  k = k1 + 4 k2:
+//   stage A: 4 x 4 DFT over (r1, c1), twiddle W_N^(r2 kr1 + c2 kc1)
+//   stage B: M-point DFT over r2 -> kr2
+//   stage C: M-point DFT over c2 -> kc2
+// so the spectrum element (kr1 + 4 kr2, kc1 + 4 kc2) sits in registers of the
+// stage-C thread; the amplitudes are stored in exactly that order at scan
+// creation, which makes every HBM access of the kernel contiguous across a
+// wavefront.
+//
+// For N = 256 (512 KiB per pattern, more than one CU's LDS) the divide runs as
+// three passes: rows forward (with the prologue), columns forward + Fourier +
+// columns inverse, rows inverse (with the epilogue).
+#include <algorithm>
+
+#include "common.hpp"
+#include "params.hpp"
+
+namespace pty {
+
+__device__ __forceinline__ float2 update_x(float2 z, float2 yo, float2 xo, float al, float be, float ga) {
+  // x_k = alpha z + beta y + gamma x, evaluated in one fixed order everywhere
+  float2 r;
+  r.x = fmaf(ga, xo.x, fmaf(be, yo.x, al * z.x));
+  r.y = fmaf(ga, xo.y, fmaf(be, yo.y, al * z.y));
+  return r;
+}
+
+__device__ __forceinline__ float2 fourier_op(float2 X, float A, float c, float one_minus_c, float inv_n2,
+                                             double& ef_num, double& ef_den) {
+  const float m2 = cnorm(X);
+  const double d = double(sqrtf(m2)) - double(A);
+  ef_num += d * d;
+  ef_den += double(A) * double(A);
+  if (m2 > 0.0f) {
+    const float f = fmaf(c * A, rsqrtf(m2), one_minus_c) * inv_n2;
+    return cscale(X, f);
+  }
+  return make_float2(c * A * inv_n2, 0.0f);
+}
+
+template <int N, int T>
+struct DivGeom {
+  static constexpr int M = N / 4;
+  static constexpr int E = N * N / T;      // complex values per thread
+  static constexpr int SA = E / 16;        // stage-A tasks per thread
+  static constexpr int SB = E / M;         // stage-B / C tasks per thread
+  static constexpr int STRIDE = 4 * N + 1; // LDS plane pitch (odd: conflict-free strided access)
+  static constexpr int LDS = M * STRIDE;
+  static_assert(SA >= 1 && SB >= 1 && SA * 16 == E && SB * M == E, "geometry");
+};
+
+template <int N, int T, class St>
+__global__ __launch_bounds__(T) void divide_fused_kernel(DivideParams p) {
+  using G = DivGeom<N, T>;
+  constexpr int M = G::M, E = G::E, SA = G::SA, SB = G::SB, STRIDE = G::STRIDE;
+  __shared__ float2 lds[G::LDS];
+  __shared__ double red[MF_COUNT * (T / 64)];
+
+  const int tid = threadIdx.x;
+  const int j = p.j_begin + blockIdx.x;
+  const size_t base = size_t(j) * N * N;
+  const int2 pj = p.pos[j];
+  using elem = typename St::elem;
+  elem* __restrict__ xs = reinterpret_cast<elem*>(p.x);
+  elem* __restrict__ ys = reinterpret_cast<elem*>(p.y);
+  const float2* __restrict__ tw = p.tw;
+
+  float2 v[E];
+  double acc[MF_COUNT];
+#pragma unroll
+  for (int q = 0; q < MF_COUNT; ++q) acc[q] = 0.0;
+
+  // ---- prologue (stage-A layout): form x_k --------------------------------
+  static_for<0, SA>([&](auto s) {
+    const int qa = tid + T * s.value;
+    const int r2 = qa / M, c2 = qa % M;
+    static_for<0, 16>([&](auto e) {
+      constexpr int r1 = e.value / 4, c1 = e.value % 4;
+      const int r = r2 + M * r1, c = c2 + M * c1;
+      const int idx = r * N + c;
+      const float2 z = cmul(p.probe[idx], p.obj[size_t(pj.x + r) * p.obj_w + (pj.y + c)]);
+      float2 xo = make_float2(0.f, 0.f), yo = make_float2(0.f, 0.f);
+      if (p.read_x) xo = St::load(xs, base + idx, p.inv_scale);
+      if (p.read_y) yo = St::load(ys, base + idx, p.inv_scale);
+      const float2 xn = update_x(z, yo, xo, p.alpha, p.beta, p.gamma);
+      if (p.prev_ec) {
+        const double dr = double(z.x) - double(yo.x), di = double(z.y) - double(yo.y);
+        acc[MF_EC_NUM] += dr * dr + di * di;
+        acc[MF_EC_DEN] += double(yo.x) * yo.x + double(yo.y) * yo.y;
+      }
+      if (p.prev_dx) {
+        const double dr = double(xn.x) - double(xo.x), di = double(xn.y) - double(xo.y);
+        acc[MF_DX_NUM] += dr * dr + di * di;
+        acc[MF_DX_DEN] += double(xo.x) * xo.x + double(xo.y) * xo.y;
+      }
+      if (p.write_x) St::store(xs, base + idx, xn, p.scale);
+      v[s.value * 16 + e.value] = xn;
+    });
+  });
+
+  // ---- stage A forward: 4x4 DFT, twiddles -----------------------------------
+  static_for<0, SA>([&](auto s) {
+    dft4x4_reg<false, s.value * 16>(v);
+    const int qa = tid + T * s.value;
+    const int r2 = qa / M, c2 = qa % M;
+    const float2 wr1 = tw[r2], wr2 = tw[2 * r2], wr3 = tw[3 * r2];
+    const float2 wc1 = tw[c2], wc2 = tw[2 * c2], wc3 = tw[3 * c2];
+    static_for<0, 16>([&](auto e) {
+      constexpr int kr1 = e.value / 4, kc1 = e.value % 4;
+      float2 t = v[s.value * 16 + e.value];
+      if constexpr (kr1 == 1) t = cmul(t, wr1);
+      if constexpr (kr1 == 2) t = cmul(t, wr2);
+      if constexpr (kr1 == 3) t = cmul(t, wr3);
+      if constexpr (kc1 == 1) t = cmul(t, wc1);
+      if constexpr (kc1 == 2) t = cmul(t, wc2);
+      if constexpr (kc1 == 3) t = cmul(t, wc3);
+      v[s.value * 16 + e.value] = t;
+    });
+  });
+
+  // ---- exchange A -> B: element (r2, kk, c2) at r2*STRIDE + kk*M + c2 --------
+  static_for<0, SA>([&](auto s) {
+    const int qa = tid + T * s.value;
+    const int r2 = qa / M, c2 = qa % M;
+    static_for<0, 16>([&](auto e) { lds[r2 * STRIDE + e.value * M + c2] = v[s.value * 16 + e.value]; });
+  });
+  __syncthreads();
+  static_for<0, SB>([&](auto s) {
+    const int qb = tid + T * s.value;
+    static_for<0, M>([&](auto r2) { v[s.value * M + r2.value] = lds[r2.value * STRIDE + qb]; });
+  });
+  // ---- stage B forward: DFT over r2 -----------------------------------------
+  static_for<0, SB>([&](auto s) { dft_reg<M, false, 1, s.value * M>(v); });
+  __syncthreads();
+  // ---- exchange B -> C: element (c2, kk, kr2) at c2*STRIDE + kk*M + kr2 ------
+  static_for<0, SB>([&](auto s) {
+    const int qb = tid + T * s.value;
+    const int kk = qb / M, c2 = qb % M;
+    static_for<0, M>([&](auto kr2) { lds[c2 * STRIDE + kk * M + kr2.value] = v[s.value * M + kr2.value]; });
+  });
+  __syncthreads();
+  static_for<0, SB>([&](auto s) {
+    const int qc = tid + T * s.value;
+    static_for<0, M>([&](auto c2) { v[s.value * M + c2.value] = lds[c2.value * STRIDE + qc]; });
+  });
+  // ---- stage C forward, Fourier-space relaxed projection, stage C inverse ----
+  const float c = p.c, omc = 1.0f - p.c, inv_n2 = 1.0f / float(N * N);
+  static_for<0, SB>([&](auto s) {
+    dft_reg<M, false, 1, s.value * M>(v);
+    const int qc = tid + T * s.value;
+    static_for<0, M>([&](auto kc2) {
+      const float A = p.amp[base + size_t(kc2.value) * (4 * N) + qc];
+      v[s.value * M + kc2.value] =
+          fourier_op(v[s.value * M + kc2.value], A, c, omc, inv_n2, acc[MF_EF_NUM], acc[MF_EF_DEN]);
+    });
+    dft_reg<M, true, 1, s.value * M>(v);
+  });
+  __syncthreads();
+  // ---- exchange C -> B -------------------------------------------------------
+  static_for<0, SB>([&](auto s) {
+    const int qc = tid + T * s.value;
+    static_for<0, M>([&](auto c2) { lds[c2.value * STRIDE + qc] = v[s.value * M + c2.value]; });
+  });
+  __syncthreads();
+  static_for<0, SB>([&](auto s) {
+    const int qb = tid + T * s.value;
+    const int kk = qb / M, c2 = qb % M;
+    static_for<0, M>([&](auto kr2) { v[s.value * M + kr2.value] = lds[c2 * STRIDE + kk * M + kr2.value]; });
+  });
+  // ---- stage B inverse -------------------------------------------------------
+  static_for<0, SB>([&](auto s) { dft_reg<M, true, 1, s.value * M>(v); });
+  __syncthreads();
+  // ---- exchange B -> A -------------------------------------------------------
+  static_for<0, SB>([&](auto s) {
+    const int qb = tid + T * s.value;
+    static_for<0, M>([&](auto r2) { lds[r2.value * STRIDE + qb] = v[s.value * M + r2.value]; });
+  });
+  __syncthreads();
+  static_for<0, SA>([&](auto s) {
+    const int qa = tid + T * s.value;
+    const int r2 = qa / M, c2 = qa % M;
+    static_for<0, 16>([&](auto e) { v[s.value * 16 + e.value] = lds[r2 * STRIDE + e.value * M + c2]; });
+  });
+  // ---- stage A inverse: conjugate twiddles, 4x4 inverse DFT, store y ---------
+  static_for<0, SA>([&](auto s) {
+    const int qa = tid + T * s.value;
+    const int r2 = qa / M, c2 = qa % M;
+    const float2 wr1 = tw[r2], wr2 = tw[2 * r2], wr3 = tw[3 * r2];
+    const float2 wc1 = tw[c2], wc2 = tw[2 * c2], wc3 = tw[3 * c2];
+    static_for<0, 16>([&](auto e) {
+      constexpr int kr1 = e.value / 4, kc1 = e.value % 4;
+      float2 t = v[s.value * 16 + e.value];
+      if constexpr (kr1 == 1) t = cmulc(t, wr1);
+      if constexpr (kr1 == 2) t = cmulc(t, wr2);
+      if constexpr (kr1 == 3) t = cmulc(t, wr3);
+      if constexpr (kc1 == 1) t = cmulc(t, wc1);
+      if constexpr (kc1 == 2) t = cmulc(t, wc2);
+      if constexpr (kc1 == 3) t = cmulc(t, wc3);
+      v[s.value * 16 + e.value] = t;
+    });
+    dft4x4_reg<true, s.value * 16>(v);
+    static_for<0, 16>([&](auto e) {
+      constexpr int r1 = e.value / 4, c1 = e.value % 4;
+      const int idx = (r2 + M * r1) * N + (c2 + M * c1);
+      St::store(ys, base + idx, v[s.value * 16 + e.value], p.scale);
+    });
+  });
+
+  // ---- per-pattern metric partials -----------------------------------------
+  block_sum<MF_COUNT, T>(acc, red);
+  if (tid < MF_COUNT) p.met[size_t(j) * p.nslot * MF_COUNT + tid] = acc[tid];
+}
+
+// ---------------------------------------------------------------------------
+// N = 256: three passes.  A work-group handles 16 rows (or 16 columns) of one
+// pattern, 16 threads per line, 16 values per thread; a line's 256-point DFT
+// is 16 x 16 with one LDS exchange inside the group.
+// ---------------------------------------------------------------------------
+constexpr int L256 = 256;
+constexpr int LP = 17;                 // padded pitch of a 16 x 16 exchange tile
+constexpr int LT = 16 * LP;            // one line's exchange tile
+
+template <class St>
+__global__ __launch_bounds__(256) void rows256_fwd_kernel(DivideParams p) {
+  __shared__ float2 lds[16 * LT];
+  __shared__ double red[MF_COUNT * 4];
+  const int tid = threadIdx.x;
+  const int t = tid & 15, rl = tid >> 4;
+  const int r = blockIdx.x * 16 + rl;
+  const int j = p.j_begin + blockIdx.y;
+  const size_t base = size_t(j) * L256 * L256;
+  const int2 pj = p.pos[j];
+  using elem = typename St::elem;
+  elem* __restrict__ xs = reinterpret_cast<elem*>(p.x);
+  const elem* ys = reinterpret_cast<const elem*>(p.y);  // may alias p.tmp
+  float2 v[16];
+  double acc[MF_COUNT];
+#pragma unroll
+  for (int q = 0; q < MF_COUNT; ++q) acc[q] = 0.0;
+
+  // prologue: column c = t + 16 c1
+  static_for<0, 16>([&](auto c1) {
+    const int c = t + 16 * c1.value;
+    const int idx = r * L256 + c;
+    const float2 z = cmul(p.probe[idx], p.obj[size_t(pj.x + r) * p.obj_w + (pj.y + c)]);
+    float2 xo = make_float2(0.f, 0.f), yo = make_float2(0.f, 0.f);
+    if (p.read_x) xo = St::load(xs, base + idx, p.inv_scale);
+    if (p.read_y) yo = St::load(ys, base + idx, p.inv_scale);
+    const float2 xn = update_x(z, yo, xo, p.alpha, p.beta, p.gamma);
+    if (p.prev_ec) {
+      const double dr = double(z.x) - double(yo.x), di = double(z.y) - double(yo.y);
+      acc[MF_EC_NUM] += dr * dr + di * di;
+      acc[MF_EC_DEN] += double(yo.x) * yo.x + double(yo.y) * yo.y;
+    }
+    if (p.prev_dx) {
+      const double dr = double(xn.x) - double(xo.x), di = double(xn.y) - double(xo.y);
+      acc[MF_DX_NUM] += dr * dr + di * di;
+      acc[MF_DX_DEN] += double(xo.x) * xo.x + double(xo.y) * xo.y;
+    }
+    if (p.write_x) St::store(xs, base + idx, xn, p.scale);
+    v[c1.value] = xn;
+  });
+  dft_reg<16, false>(v);                                  // over c1 -> kc1
+  static_for<1, 16>([&](auto k) { v[k.value] = cmul(v[k.value], p.tw[t * k.value]); });
+  static_for<0, 16>([&](auto k) { lds[rl * LT + k.value * LP + t] = v[k.value]; });
+  __syncthreads();
+  static_for<0, 16>([&](auto c2) { v[c2.value] = lds[rl * LT + t * LP + c2.value]; });
+  dft_reg<16, false>(v);                                  // over c2 -> kc2; thread t = kc1
+  static_for<0, 16>([&](auto k2) { p.tmp[base + r * L256 + t + 16 * k2.value] = v[k2.value]; });
+
+  block_sum<MF_COUNT, 256>(acc, red);
+  if (tid >= MF_EC_NUM && tid < MF_COUNT)
+    p.met[(size_t(j) * p.nslot + blockIdx.x) * MF_COUNT + tid] = acc[tid];
+}
+
+__global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
+  __shared__ float2 lds[16 * LT];
+  __shared__ double red[2 * 4];
+  const int tid = threadIdx.x;
+  const int cl = tid & 15, t = tid >> 4;
+  const int col = blockIdx.x * 16 + cl;
+  const int j = p.j_begin + blockIdx.y;
+  const size_t base = size_t(j) * L256 * L256;
+  float2 v[16];
+  // rows r = t + 16 r1
+  static_for<0, 16>([&](auto r1) { v[r1.value] = p.tmp[base + (t + 16 * r1.value) * L256 + col]; });
+  dft_reg<16, false>(v);                                  // over r1 -> kr1
+  static_for<1, 16>([&](auto k) { v[k.value] = cmul(v[k.value], p.tw[t * k.value]); });
+  static_for<0, 16>([&](auto k) { lds[cl * LT + k.value * LP + t] = v[k.value]; });
+  __syncthreads();
+  static_for<0, 16>([&](auto r2) { v[r2.value] = lds[cl * LT + t * LP + r2.value]; });
+  dft_reg<16, false>(v);                                  // over r2 -> kr2; thread t = kr1
+  double acc[2] = {0.0, 0.0};
+  const float c = p.c, omc = 1.0f - p.c, inv_n2 = 1.0f / float(L256 * L256);
+  static_for<0, 16>([&](auto k2) {
+    const int kr = t + 16 * k2.value;
+    const float A = p.amp[base + size_t(kr) * L256 + col];
+    v[k2.value] = fourier_op(v[k2.value], A, c, omc, inv_n2, acc[0], acc[1]);
+  });
+  dft_reg<16, true>(v);                                   // over kr2 -> r2
+  __syncthreads();
+  static_for<0, 16>([&](auto r2) { lds[cl * LT + t * LP + r2.value] = v[r2.value]; });
+  __syncthreads();
+  static_for<0, 16>([&](auto k) { v[k.value] = lds[cl * LT + k.value * LP + t]; });  // thread t = r2
+  static_for<1, 16>([&](auto k) { v[k.value] = cmulc(v[k.value], p.tw[t * k.value]); });
+  dft_reg<16, true>(v);                                   // over kr1 -> r1
+  static_for<0, 16>([&](auto r1) { p.tmp[base + (t + 16 * r1.value) * L256 + col] = v[r1.value]; });
+
+  block_sum<2, 256>(acc, red);
+  if (tid < 2) p.met[(size_t(j) * p.nslot + blockIdx.x) * MF_COUNT + tid] = acc[tid];
+}
+
+template <class St>
+__global__ __launch_bounds__(256) void rows256_inv_kernel(DivideParams p) {
+  __shared__ float2 lds[16 * LT];
+  const int tid = threadIdx.x;
+  const int t = tid & 15, rl = tid >> 4;
+  const int r = blockIdx.x * 16 + rl;
+  const int j = p.j_begin + blockIdx.y;
+  const size_t base = size_t(j) * L256 * L256;
+  using elem = typename St::elem;
+  elem* __restrict__ ys = reinterpret_cast<elem*>(p.y);
+  float2 v[16];
+  // thread t = kc1 holds kc2
+  static_for<0, 16>([&](auto k2) { v[k2.value] = p.tmp[base + r * L256 + t + 16 * k2.value]; });
+  dft_reg<16, true>(v);                                   // over kc2 -> c2
+  static_for<0, 16>([&](auto c2) { lds[rl * LT + c2.value * LP + t] = v[c2.value]; });
+  __syncthreads();
+  static_for<0, 16>([&](auto k1) { v[k1.value] = lds[rl * LT + t * LP + k1.value]; });  // thread t = c2
+  static_for<1, 16>([&](auto k) { v[k.value] = cmulc(v[k.value], p.tw[t * k.value]); });
+  dft_reg<16, true>(v);                                   // over kc1 -> c1
+  static_for<0, 16>([&](auto c1) {
+    St::store(ys, base + r * L256 + t + 16 * c1.value, v[c1.value], p.scale);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Materialise the pending update and/or the previous iteration's metrics:
+// x_k = alpha P S_j O + beta y_{k-1} + gamma x_{k-1} (same arithmetic as the
+// divide prologue).  One block per pattern; slot 0 gets the sums and the other
+// slots are cleared.
+// ---------------------------------------------------------------------------
+template <class St>
+__global__ __launch_bounds__(256) void flush_kernel(FlushParams p) {
+  __shared__ double red[4 * 4];
+  const int j = blockIdx.x;
+  const int N = p.N;
+  const size_t base = size_t(j) * N * N;
+  const int2 pj = p.pos[j];
+  using elem = typename St::elem;
+  elem* xs = reinterpret_cast<elem*>(p.x);
+  const elem* ys = reinterpret_cast<const elem*>(p.y);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int idx = threadIdx.x; idx < N * N; idx += 256) {
+    const int r = idx / N, c = idx % N;
+    const float2 z = cmul(p.probe[idx], p.obj[size_t(pj.x + r) * p.obj_w + (pj.y + c)]);
+    float2 xo = make_float2(0.f, 0.f), yo = make_float2(0.f, 0.f);
+    if (p.read_x) xo = St::load(xs, base + idx, p.inv_scale);
+    if (p.read_y) yo = St::load(ys, base + idx, p.inv_scale);
+    const float2 xn = update_x(z, yo, xo, p.alpha, p.beta, p.gamma);
+    double dr = double(z.x) - double(yo.x), di = double(z.y) - double(yo.y);
+    acc[0] += dr * dr + di * di;
+    acc[1] += double(yo.x) * yo.x + double(yo.y) * yo.y;
+    dr = double(xn.x) - double(xo.x);
+    di = double(xn.y) - double(xo.y);
+    acc[2] += dr * dr + di * di;
+    acc[3] += double(xo.x) * xo.x + double(xo.y) * xo.y;
+    if (p.write_x) St::store(xs, base + idx, xn, p.scale);
+  }
+  block_sum<4, 256>(acc, red);
+  for (int q = threadIdx.x; q < p.nslot * MF_COUNT; q += 256) {
+    const int slot = q / MF_COUNT, f = q % MF_COUNT;
+    double v = 0.0;
+    if (slot == 0 && f >= MF_EC_NUM) v = acc[f - MF_EC_NUM];
+    p.met[size_t(j) * p.nslot * MF_COUNT + q] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <int N, int T, class St>
+static hipError_t launch_fused(const DivideParams& p, int n_patterns, hipStream_t s) {
+  hipLaunchKernelGGL((divide_fused_kernel<N, T, St>), dim3(n_patterns), dim3(T), 0, s, p);
+  return hipGetLastError();
+}
+
+template <class St>
+static hipError_t launch_256(const DivideParams& p, int n_patterns, hipStream_t s) {
+  const dim3 grid(16, n_patterns);
+  hipLaunchKernelGGL((rows256_fwd_kernel<St>), grid, dim3(256), 0, s, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cols256_kernel, grid, dim3(256), 0, s, p);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((rows256_inv_kernel<St>), grid, dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+template <class St>
+static hipError_t launch_divide_t(int n, const DivideParams& p, int n_patterns, hipStream_t s) {
+  switch (n) {
+    case 32: return launch_fused<32, 64, St>(p, n_patterns, s);
+    case 64: return launch_fused<64, 256, St>(p, n_patterns, s);
+    case 128: return launch_fused<128, 512, St>(p, n_patterns, s);
+    case 256: return launch_256<St>(p, n_patterns, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_divide(int n, int fp16, const DivideParams& p, int n_patterns, hipStream_t s) {
+  if (n_patterns <= 0) return hipSuccess;
+  return fp16 ? launch_divide_t<StoreF16>(n, p, n_patterns, s) : launch_divide_t<StoreF32>(n, p, n_patterns, s);
+}
+
+hipError_t launch_flush(int fp16, const FlushParams& p, int J, hipStream_t s) {
+  if (J <= 0) return hipSuccess;
+  if (fp16) hipLaunchKernelGGL(flush_kernel<StoreF16>, dim3(J), dim3(256), 0, s, p);
+  else hipLaunchKernelGGL(flush_kernel<StoreF32>, dim3(J), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+int divide_slots(int n) { return n == 256 ? 16 : 1; }
+bool divide_supported(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
+
+// Amplitudes sqrt(I) in the order the divide kernel reads them.  N <= 128:
+// amp[j][kc2][qc] with qc = (kr1*4 + kc1)*M + kr2 for the spectrum element
+// (kr1 + 4 kr2, kc1 + 4 kc2); N = 256: natural order.  Values that are not
+// finite or are negative are counted in *bad.
+__global__ void amp_prepare_kernel(const float* __restrict__ I, float* __restrict__ amp, int n, int J,
+                                   int* bad) {
+  const size_t nn = size_t(n) * n;
+  const size_t total = nn * J;
+  const int M = n / 4;
+  for (size_t g = blockIdx.x * size_t(blockDim.x) + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
+    const size_t j = g / nn;
+    const int rem = int(g % nn);
+    size_t src;
+    if (n == 256) {
+      src = g;
+    } else {
+      const int kc2 = rem / (4 * n), qc = rem % (4 * n);
+      const int kk = qc / M, kr2 = qc % M;
+      const int kr = kk / 4 + 4 * kr2, kc = kk % 4 + 4 * kc2;
+      src = j * nn + size_t(kr) * n + kc;
+    }
+    const float iv = I[src];
+    if (!(iv >= 0.0f) || !isfinite(iv)) {
+      atomicAdd(bad, 1);
+      amp[g] = 0.0f;
+    } else {
+      amp[g] = float(sqrt(double(iv)));
+    }
+  }
+}
+
+hipError_t launch_amp_prepare(int n, const float* intensity, float* amp, int J, int* bad, hipStream_t s) {
+  const size_t total = size_t(n) * n * J;
+  const int blocks = int(std::min<size_t>((total + 255) / 256, 65536));
+  hipLaunchKernelGGL(amp_prepare_kernel, dim3(blocks), dim3(256), 0, s, intensity, amp, n, J, bad);
+  return hipGetLastError();
+}
+
+}  // namespace pty

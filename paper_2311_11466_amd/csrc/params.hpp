@@ -1,0 +1,111 @@
+// Kernel parameter blocks (plain structs, passed by value) and launcher
+// declarations shared by the host engine and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pty {
+
+// per-slot metric partials, float64:
+enum MetricField { MF_EF_NUM = 0, MF_EF_DEN, MF_EC_NUM, MF_EC_DEN, MF_DX_NUM, MF_DX_DEN, MF_COUNT };
+// ring entry: iteration, fourier_err, consistency_err, change
+constexpr int kRingFields = 4;
+
+struct DivideParams {
+  const float2* obj;      // [H][W]
+  const float2* probe;    // [N][N]
+  const int2* pos;        // [J] (row, col)
+  const float* amp;       // sqrt(I) in the layout of the consuming kernel
+  const float2* tw;       // tw[m] = exp(-2 pi i m / N), m < N
+  void* x;                // exit waves, storage format of the kernel
+  void* y;
+  float2* tmp;            // N = 256: float32 intermediate (may alias y)
+  int obj_w;
+  int j_begin;
+  // prologue: x_k = alpha * P S_j O + beta * y_{k-1} + gamma * x_{k-1}
+  float alpha, beta, gamma;
+  float c;                // divide relaxation
+  float scale, inv_scale; // float16 storage scale and its inverse
+  int read_x, read_y, write_x;
+  int prev_ec, prev_dx;   // accumulate consistency / change partials of the previous iteration
+  double* met;            // [J][nslot][MF_COUNT]
+  int nslot;
+};
+
+struct ObjParams {
+  const void* y;
+  float inv_scale;
+  const float2* probe;
+  const int2* pos;
+  const int* tile_off;    // [n_tiles + 1]
+  const int* tile_list;   // ascending scan indices per tile
+  float2* obj;
+  int H, W, N, tiles_x, n_tiles;
+  float* tile_max;        // [n_tiles] max |O_new|^2 of each tile
+  const float* pmax_part; // [npb] partial maxima of |P|^2
+  int npb;
+  double tau;
+};
+
+struct ProbeParams {
+  const void* y;
+  float inv_scale;
+  const float2* obj;
+  const int2* pos;
+  int N, W, J, chunk, G;
+  double* part;           // [3][G][N*N]: Re N_P, Im N_P, D_P
+};
+
+struct FinalParams {
+  const double* part;     // as ProbeParams::part
+  float2* probe;
+  float* pmax_part;
+  const float* tile_max;
+  int n_tiles, N, G, npb;
+  double tau;
+  int first_block;        // npb to run the metrics block only
+  // metrics
+  const double* met;
+  int J, nslot;
+  double* ring;           // [cap][kRingFields]
+  int cap;
+  long long k_cur;        // iteration whose Fourier error is in met (-1: none)
+  long long k_prev;       // iteration whose consistency / change are in met (-1: none)
+  int ec_ok, dx_ok;
+};
+
+struct FlushParams {
+  const float2* obj;
+  const float2* probe;
+  const int2* pos;
+  void* x;
+  const void* y;
+  int N, obj_w;
+  float alpha, beta, gamma;
+  float scale, inv_scale;
+  int read_x, read_y;     // a buffer not read counts as zero
+  int write_x;
+  double* met;
+  int nslot;
+};
+
+// ---- launchers (return hipGetLastError() of the launch) ----
+hipError_t launch_divide(int n, int fp16, const DivideParams& p, int n_patterns, hipStream_t s);
+hipError_t launch_object_update(int fp16, const ObjParams& p, hipStream_t s);
+hipError_t launch_probe_partial(int fp16, const ProbeParams& p, hipStream_t s);
+hipError_t launch_probe_final(const FinalParams& p, int update_probe, hipStream_t s);
+hipError_t launch_flush(int fp16, const FlushParams& p, int J, hipStream_t s);
+hipError_t launch_metrics_only_final(const FinalParams& p, hipStream_t s);
+hipError_t launch_amp_prepare(int n, const float* intensity, float* amp, int J, int* bad, hipStream_t s);
+hipError_t launch_max_abs2_parts(const float2* a, size_t count, float* parts, int nparts, hipStream_t s);
+hipError_t launch_convert_state(int fp16, int to_store, const float2* src, void* dst_store,
+                                const void* src_store, float2* dst, size_t count, float scale,
+                                float inv_scale, hipStream_t s);
+
+// divide-kernel geometry helpers for the host
+int divide_slots(int n);                 // metric slots per pattern
+bool divide_supported(int n);
+
+}  // namespace pty

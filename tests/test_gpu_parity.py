@@ -1,0 +1,292 @@
+"""GPU parity: the HIP library against the FP64 oracle, through the C ABI.
+
+Gate: one iteration from an identical state (the oracle state rounded to
+float32 and loaded with set_state) must give x_{k+1}, y_k = P^c_D x_k, O_{k+1}
+and P_{k+1} within 1e-5 relative L2 of the oracle's iteration from the same
+rounded state.  Several iterations from the start are compared with a looser
+bound, since a non-convex iteration amplifies rounding differences.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_helpers import (rel_l2, gpu_scan, amp32, covered_mask, oracle_state_after, round_state,
+                         to_dev)
+from oracle import pty_oracle as po
+from ptysynth import make_scan
+from ptysynth.scans import small_config
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+PRESETS = [("DC", 0.0), ("AR", 0.0), ("DR", 0.0), ("SF", 0.0), ("RAAR", 0.75), ("RRR", 0.5),
+           ("TLAMBDA", 0.5)]
+CUSTOM = [(0.3, 1.7, 0.6), (1.25, 0.5, 1.5)]
+
+_SCANS = {}
+
+
+def get_scan(name):
+    if name not in _SCANS:
+        if name == "tiny_n32":
+            _SCANS[name] = make_scan("tiny_n32")
+        elif name == "p64":      # 5 x 5 raster on a 172 x 172 object: ragged 64 x 16 tiles
+            _SCANS[name] = make_scan(small_config("p64", 64, 5, 24, jitter=2, photons=1e6, seed=31))
+        elif name == "p128":     # 4 x 4 raster on a 260 x 260 object
+            _SCANS[name] = make_scan(small_config("p128", 128, 4, 40, jitter=2, photons=1e6, seed=41))
+        elif name == "p256":     # 3 x 3 raster on a 430 x 430 object
+            _SCANS[name] = make_scan(small_config("p256", 256, 3, 80, jitter=3, photons=1e5, seed=51))
+        else:
+            raise KeyError(name)
+    return _SCANS[name]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def single_step(scan, abc, blind=True, k_start=2, storage="fp32"):
+    """Run one GPU iteration and one oracle iteration from the same float32 state."""
+    st = round_state(oracle_state_after(scan, k_start, po.preset("RAAR", 0.75), blind=blind))
+    g = gpu_scan(scan, storage=storage, blind=blind)
+    g.set_state(to_dev(st.x.astype(np.complex64)), None, to_dev(st.obj.astype(np.complex64)),
+                to_dev(st.probe.astype(np.complex64)))
+    g.set_algorithm(*abc)
+    g.iterate(1)
+    x1, y0, o1, p1 = (t.cpu().numpy() for t in g.get_state())
+    m = g.metrics(allow_diverged=True)
+    new, info = po.step(st, amp32(scan), scan.pos, *abc, blind=blind)
+    g.close()
+    return (x1, y0, o1, p1, m), (new, info)
+
+
+def check_step(scan, got, ref, tol=TOL, what=""):
+    x1, y0, o1, p1, m = got
+    new, info = ref
+    cov = covered_mask(scan)
+    errs = {"y": rel_l2(y0, info["y"]), "x": rel_l2(x1, new.x), "obj": rel_l2(o1, new.obj, cov),
+            "probe": rel_l2(p1, new.probe)}
+    say(what, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, (what, k, v)
+    # pixels no window covers keep their value exactly
+    assert np.array_equal(o1[~cov], new.obj[~cov].astype(np.complex64))
+    om = info["metrics"]
+    for key in ("fourier_err", "consistency_err", "change"):
+        assert abs(m[key] - om[key]) <= 1e-4 * abs(om[key]) + 1e-12, (what, key, m[key], om[key])
+
+
+@pytest.mark.parametrize("name,param", PRESETS)
+def test_single_step_presets_n32(name, param):
+    scan = get_scan("tiny_n32")
+    abc = po.preset(name, param)
+    say("case: single step tiny_n32", name, param)
+    got, ref = single_step(scan, abc)
+    check_step(scan, got, ref, what=f"n32 {name}")
+
+
+@pytest.mark.parametrize("abc", CUSTOM)
+def test_single_step_custom_abc(abc):
+    scan = get_scan("tiny_n32")
+    say("case: single step tiny_n32 abc", abc)
+    got, ref = single_step(scan, abc)
+    check_step(scan, got, ref, what=f"n32 {abc}")
+
+
+@pytest.mark.parametrize("cfg", ["p64", "p128", "p256"])
+@pytest.mark.parametrize("name,param", [("RAAR", 0.75), ("DC", 0.0), ("SF", 0.0)])
+def test_single_step_sizes(cfg, name, param):
+    scan = get_scan(cfg)
+    say("case: single step", cfg, name, param)
+    got, ref = single_step(scan, po.preset(name, param))
+    check_step(scan, got, ref, what=f"{cfg} {name}")
+
+
+@pytest.mark.parametrize("cfg", ["tiny_n32", "p128", "p256"])
+def test_single_step_known_probe(cfg):
+    scan = get_scan(cfg)
+    say("case: known probe", cfg)
+    got, ref = single_step(scan, po.preset("DR"), blind=False)
+    check_step(scan, got, ref, what=f"{cfg} known")
+    assert np.array_equal(got[3], ref[0].probe.astype(np.complex64))
+
+
+@pytest.mark.parametrize("cfg,abc,n_iter,tol", [
+    ("tiny_n32", po.preset("RAAR", 0.75), 20, 1e-4),
+    ("tiny_n32", po.preset("DC"), 20, 1e-4),
+    ("p64", po.preset("RRR", 0.5), 10, 1e-4),
+    ("p256", po.preset("DR"), 5, 1e-4),
+])
+def test_trajectory(cfg, abc, n_iter, tol):
+    """Free-running iterations from the start: state and metric history."""
+    scan = get_scan(cfg)
+    say("case: trajectory", cfg, abc, n_iter)
+    g = gpu_scan(scan)
+    g.set_algorithm(*abc)
+    g.iterate(n_iter)
+    x, y, o, p = (t.cpu().numpy() for t in g.get_state())
+    hist = g.metric_history()
+    g.close()
+    st = po.init_state(scan.obj0.astype(np.complex64).astype(np.complex128),
+                       scan.probe0.astype(np.complex64).astype(np.complex128), scan.pos)
+    st = po.run(st, amp32(scan), scan.pos, *abc, n_iter, blind=True)
+    cov = covered_mask(scan)
+    errs = (rel_l2(x, st.x), rel_l2(o, st.obj, cov), rel_l2(p, st.probe))
+    say("  trajectory errors x/obj/probe", errs)
+    assert max(errs) <= tol
+    assert len(hist) == n_iter
+    for gm, om in zip(hist, st.history):
+        assert gm["iteration"] == om["iteration"]
+        assert abs(gm["fourier_err"] - om["fourier_err"]) <= 1e-3 * om["fourier_err"] + 1e-12
+
+
+def test_fixed_point_noise_free():
+    """The true object, probe and exit waves of noise-free data are a fixed point."""
+    scan = get_scan("tiny_n32")
+    say("case: fixed point")
+    g = gpu_scan(scan, obj0=scan.obj_true, probe0=scan.probe_true)
+    x_true = po.exit_waves(scan.obj_true, scan.probe_true, scan.pos)
+    for name, prm in PRESETS:
+        g.set_state(to_dev(x_true.astype(np.complex64)), None, to_dev(scan.obj_true.astype(np.complex64)),
+                    to_dev(scan.probe_true.astype(np.complex64)))
+        g.set_algorithm_named(name, prm)
+        g.iterate(1)
+        x, y, o, p = (t.cpu().numpy() for t in g.get_state())
+        assert rel_l2(x, x_true) < 1e-5, name
+        assert rel_l2(p, scan.probe_true) < 1e-5, name
+        m = g.metrics()
+        assert m["fourier_err"] < 1e-10 and m["consistency_err"] < 1e-10, (name, m)
+    g.close()
+
+
+def test_deterministic_bitwise():
+    scan = get_scan("p128")
+    say("case: determinism")
+    out = []
+    for _ in range(2):
+        g = gpu_scan(scan)
+        g.set_algorithm_named("RAAR", 0.75)
+        g.iterate(4)
+        out.append([t.cpu().numpy() for t in g.get_state()])
+        g.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("cfg", ["tiny_n32", "p256"])
+def test_checkpoint_resume_bitwise(cfg):
+    scan = get_scan(cfg)
+    say("case: checkpoint", cfg)
+    a = gpu_scan(scan)
+    a.set_algorithm_named("DR")
+    a.iterate(6)
+    ref = [t.cpu().numpy() for t in a.get_state()]
+    a.close()
+    b = gpu_scan(scan)
+    b.set_algorithm_named("DR")
+    b.iterate(3)
+    ck = b.get_state()
+    b.close()
+    c = gpu_scan(scan)
+    c.set_state(*ck)
+    c.set_algorithm_named("DR")
+    c.iterate(3)
+    got = [t.cpu().numpy() for t in c.get_state()]
+    c.close()
+    for name, r, q in zip("xyop", ref, got):
+        assert np.array_equal(r.view(np.uint32), q.view(np.uint32)), name
+
+
+def test_probe_update_start():
+    scan = get_scan("tiny_n32")
+    say("case: probe_update_start")
+    g = gpu_scan(scan, probe_update_start=3)
+    g.set_algorithm_named("DC")
+    g.iterate(3)
+    assert np.array_equal(g.probe().cpu().numpy(), scan.probe0.astype(np.complex64))
+    g.iterate(1)
+    assert not np.array_equal(g.probe().cpu().numpy(), scan.probe0.astype(np.complex64))
+    g.close()
+
+
+def test_edge_single_position_exact_object():
+    """J = 1, object exactly N x N: every pixel covered once; ragged everywhere."""
+    rng = np.random.default_rng(5)
+    n = 32
+    obj = (rng.uniform(0.5, 1, (n, n)) * np.exp(1j * rng.uniform(-1, 1, (n, n))))
+    probe = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    pos = np.zeros((1, 2), np.int32)
+    inten = np.abs(np.fft.fft2(obj * probe))[None] ** 2 * rng.uniform(0.5, 1.5, (1, n, n))
+
+    class S:  # minimal scan record for the helpers
+        pass
+    s = S()
+    s.pos, s.intensity, s.obj0, s.probe0 = pos, inten, np.ones((n, n), complex), probe
+    say("case: single position")
+    g = gpu_scan(s)
+    g.set_algorithm_named("RAAR", 0.75)
+    g.iterate(1)
+    x1, y0, o1, p1 = (t.cpu().numpy() for t in g.get_state())
+    g.close()
+    st = po.init_state(np.ones((n, n)), probe.astype(np.complex64).astype(np.complex128), pos)
+    new, info = po.step(st, np.sqrt(inten.astype(np.float32).astype(np.float64)), pos,
+                        *po.preset("RAAR", 0.75))
+    assert rel_l2(y0, info["y"]) < TOL and rel_l2(x1, new.x) < TOL
+    assert rel_l2(o1, new.obj) < TOL and rel_l2(p1, new.probe) < TOL
+
+
+def test_edge_zero_wave_and_zero_data():
+    """x_j = 0 (phase taken as 0: P_D x_j = F^-1 A_j) and I_j = 0 (P_D x_j = 0)."""
+    scan = get_scan("tiny_n32")
+    say("case: zero wave / zero data")
+    inten = scan.intensity.copy()
+    inten[5] = 0.0
+
+    class S:
+        pass
+    s = S()
+    s.pos, s.intensity, s.obj0, s.probe0 = scan.pos, inten, scan.obj0, scan.probe0
+    st = round_state(oracle_state_after(scan, 1, po.preset("DC")))
+    st.x[3] = 0.0
+    g = gpu_scan(s)
+    g.set_state(to_dev(st.x.astype(np.complex64)), None, to_dev(st.obj.astype(np.complex64)),
+                to_dev(st.probe.astype(np.complex64)))
+    g.set_algorithm_named("DC")
+    g.iterate(1)
+    x1, y0, o1, p1 = (t.cpu().numpy() for t in g.get_state())
+    g.close()
+    amp = np.sqrt(inten.astype(np.float32).astype(np.float64))
+    new, info = po.step(st, amp, scan.pos, 1, 1, 1)
+    assert rel_l2(y0[3], np.fft.ifft2(amp[3])) < TOL
+    assert np.abs(y0[5]).max() == 0.0
+    assert rel_l2(y0, info["y"]) < TOL and rel_l2(o1, new.obj, covered_mask(scan)) < TOL
+
+
+def test_fp16_storage_single_step():
+    """FP16 exit-wave storage: one step from the same (FP16-representable) state.
+
+    Bound: x and y are rounded to float16 on store (unit roundoff 2^-11 ~ 4.9e-4
+    per component), so their relative L2 error is at most about 5e-4; the
+    object and probe inherit it from y.  Gate: 1e-3.
+    """
+    scan = make_scan("fp16_n32")
+    say("case: fp16 single step")
+    g = gpu_scan(scan, storage="fp16")
+    st = round_state(oracle_state_after(scan, 2, po.preset("RAAR", 0.75)))
+    g.set_state(to_dev(st.x.astype(np.complex64)), None, to_dev(st.obj.astype(np.complex64)),
+                to_dev(st.probe.astype(np.complex64)))
+    # the state the library now holds is x rounded to float16 (times its scale)
+    xs = g.get_state()[0].cpu().numpy()
+    assert rel_l2(xs, st.x) < 5e-4
+    st.x = xs.astype(np.complex128)
+    g.set_algorithm_named("RAAR", 0.75)
+    g.iterate(1)
+    x1, y0, o1, p1 = (t.cpu().numpy() for t in g.get_state())
+    g.close()
+    new, info = po.step(st, amp32(scan), scan.pos, *po.preset("RAAR", 0.75))
+    cov = covered_mask(scan)
+    errs = (rel_l2(y0, info["y"]), rel_l2(x1, new.x), rel_l2(o1, new.obj, cov), rel_l2(p1, new.probe))
+    say("  fp16 errors y/x/obj/probe", errs)
+    assert max(errs) < 1e-3
