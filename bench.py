@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Throughput of the generalised 'abc' set-projection iteration on one MI355X.
+
+A step is one full iteration of the hot path over every diffraction pattern
+of the workload: divide (the pending update, forward DFT, relaxed modulus
+projection, inverse DFT), concur (object and probe overlap consensus in
+float64) and the metric finalisation.  The metric is diffraction-pattern
+projections per second, J * steps / time, with every input resident in HBM
+before the timed region starts.
+
+Default workload: scan_n128 -- object 1024 x 1024, N = 128, J = 1024
+positions (32 x 32 raster, step 28, +-2 jitter), Poisson data at 1e6 photons
+per pattern, blind RAAR (beta = 0.75), float32 exit waves with float64
+overlap sums.  Inputs are seeded and synthetic (ptysynth).
+
+The roofline figure is for the kernel with the largest share of the step,
+timed with HIP events on the scan's stream over the timed region itself.
+
+  python bench.py [--steps K] [--warmup W] [--workload scan_n128|large_n256|tiny_n32]
+  python bench.py --summarize-pmc FETCH_CSV WRITE_CSV   (writes the traffic file under profiles/)
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
+KERNEL_NAMES = {
+    "divide": "divide_fused_kernel",
+    "divide_cols": "cols256_kernel",
+    "divide_rows_inv": "rows256_inv_kernel",
+    "object": "object_update_kernel",
+    "probe_partial": "probe_partial_kernel",
+    "probe_final": "probe_final_kernel",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{workload}.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_11466_amd", "csrc", f)
+                  for f in ("divide.hip", "concur.hip", "common.hpp", "params.hpp")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kind: str, n: int, J: int, abc, blind: bool, storage: str, full_metrics=True):
+    """HBM bytes one launch of a kernel class must move (roofline numerator).
+
+    Per pattern pixel: divide reads x_{k-1}, y_{k-1} (when needed), sqrt(I)
+    (4 B) and writes x_k, y_k; the N = 256 column pass reads and writes its
+    float32 intermediate (16 B) and reads sqrt(I); the row passes read or write
+    the intermediate (8 B) besides the exit waves; the object and probe kernels
+    read y once each.  Object/probe gathers and the float64 partial sums are
+    not counted (they are cache-resident or small).
+    """
+    a, b, _ = abc
+    e = 4 if storage == "fp16" else 8
+    rx = e if (abs(1 - a) > 0 or full_metrics) else 0
+    ry = e if (abs(a * (1 - b)) > 0 or full_metrics) else 0
+    nn = n * n * J
+    if kind == "divide":
+        if n == 256:
+            return (rx + ry + rx + 8) * nn          # rows forward: x, y in; x out; intermediate out
+        return (rx + ry + 4 + rx + e) * nn
+    if kind == "divide_cols":
+        return (8 + 4 + 8) * nn
+    if kind == "divide_rows_inv":
+        return (8 + e) * nn
+    if kind in ("object", "probe_partial"):
+        return e * nn
+    return 0
+
+
+def make_workload(name: str):
+    import numpy as np
+    from ptysynth import make_scan
+    scan = make_scan(name, intensity_dtype=np.float32)
+    return scan
+
+
+def run_cpu_baseline(scan, abc, n_iter: int):
+    """The FP64 oracle, as it stands, on the same scan for n_iter iterations."""
+    import numpy as np
+    from oracle import pty_oracle as po
+    amp = np.sqrt(scan.intensity.astype(np.float64))
+    st = po.init_state(scan.obj0, scan.probe0, scan.pos)
+    t0 = time.perf_counter()
+    po.run(st, amp, scan.pos, *abc, n_iter, blind=True)
+    dt = time.perf_counter() - t0
+    return scan.n_pos * n_iter / dt, dt
+
+
+def load_traffic(kernel: str, workload: str):
+    path = TRAFFIC_FILE.format(kernel=kernel, workload=workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != kernel_source_hash():
+        return None      # the kernel changed since the counters were taken
+    return t.get("bytes_per_launch")
+
+
+def bench(args):
+    import numpy as np
+    import torch
+    import paper_2311_11466_amd as pk
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    scan = make_workload(args.workload)
+    abc = pk.preset(args.algorithm, args.param)
+    cfg = scan.config
+    print(f"# workload {cfg.name}: object {cfg.obj_h}x{cfg.obj_w}, N={cfg.n}, J={scan.n_pos}", file=sys.stderr,
+          flush=True)
+    g = pk.Scan(torch.as_tensor(scan.pos).to(dev), torch.as_tensor(scan.intensity).to(dev),
+                torch.as_tensor(scan.obj0.astype(np.complex64)).to(dev),
+                torch.as_tensor(scan.probe0.astype(np.complex64)).to(dev),
+                storage=args.storage, blind=True, device=dev)
+    g.set_algorithm(*abc)
+    g.iterate(args.warmup)
+    torch.cuda.synchronize()
+    g.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.iterate(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile_read()
+    g.profile(False)
+    dt = t1 - t0
+    m = g.metrics(allow_diverged=True)
+    print(f"# timed {args.steps} steps in {dt * 1e3:.2f} ms; last metrics {m}", file=sys.stderr, flush=True)
+
+    kernels = {}
+    for k, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        avg_us = ms / cnt * 1e3
+        nbytes = algorithmic_bytes(k, cfg.n, scan.n_pos, abc, True, args.storage)
+        kernels[k] = {"avg_us": round(avg_us, 3), "launches": cnt,
+                      "share": round(ms / (dt * 1e3), 4),
+                      "algorithmic_bytes": nbytes,
+                      "GBs": round(nbytes / (avg_us * 1e-6) / 1e9, 1) if nbytes else None}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+    d = kernels[dom]
+    traffic = load_traffic(dom, cfg.name)
+    roofline = {"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(d["GBs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": KERNEL_NAMES[dom], "avg_us": d["avg_us"],
+                "algorithmic_bytes_per_launch": d["algorithmic_bytes"]}
+
+    if args.copy_probe:
+        # a plain copy of known size, for scaling rocprofv3 FETCH/WRITE counters
+        src = torch.empty(args.copy_probe_bytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_cpu = 3
+        rate, cpu_dt = run_cpu_baseline(scan, abc, n_cpu)
+        cpu = {"value": round(rate, 2), "unit": "projections/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n_cpu} iterations of the full {cfg.name} workload ({scan.n_pos} patterns), "
+                         f"FP64 NumPy oracle, single thread, {cpu_dt:.1f} s"}
+    value = scan.n_pos * args.steps / dt
+    line = {
+        "metric": "diffraction-pattern projections/s (P_D+P_C) at 1 GPU",
+        "value": round(value, 1),
+        "unit": "projections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32" if args.storage == "fp32" else "fp16-storage/fp32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "object": [cfg.obj_h, cfg.obj_w], "n": cfg.n, "positions": scan.n_pos,
+                   "algorithm": f"{args.algorithm}({args.param})" if args.algorithm in ("RAAR", "RRR", "TLAMBDA")
+                   else args.algorithm,
+                   "abc": list(abc), "blind": True, "storage": args.storage, "accumulate": "fp64",
+                   "photons": cfg.photons, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "metrics_last": m,
+    }
+    g.close()
+    print(json.dumps(line), flush=True)
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int):
+    """Turn two rocprofv3 --pmc counter CSVs into the traffic file bench.py reads.
+
+    FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by the
+    ratio of known bytes to the same counter's reading on the copy kernel
+    (torch's elementwise copy of copy_bytes bytes).
+    """
+    import csv
+    import statistics
+
+    def read(path, counter):
+        rows = {}
+        files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True) \
+            if os.path.isdir(path) else [path]
+        for f in files:
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r.get("Counter_Name") != counter:
+                        continue
+                    rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return rows
+    fetch = read(fetch_csv, "FETCH_SIZE")
+    write = read(write_csv, "WRITE_SIZE")
+
+    def pick(rows, key):
+        vals = [v for k, vs in rows.items() if key in k for v in vs]
+        return statistics.median(vals) if vals else None
+    copy_key = "copy"
+    f_copy = pick(fetch, copy_key)
+    w_copy = pick(write, copy_key)
+    f_scale = copy_bytes / (f_copy * 1024) if f_copy else None
+    w_scale = copy_bytes / (w_copy * 1024) if w_copy else None
+    src_hash = kernel_source_hash()
+    for cls, kname in KERNEL_NAMES.items():
+        f = pick(fetch, kname)
+        w = pick(write, kname)
+        if f is None or w is None or f_scale is None or w_scale is None:
+            continue
+        out = {"kernel": kname, "workload": workload, "source_hash": src_hash,
+               "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w,
+               "copy_bytes": copy_bytes, "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
+               "fetch_scale": f_scale, "write_scale": w_scale,
+               "bytes_per_launch": round(f * 1024 * f_scale + w * 1024 * w_scale)}
+        path = TRAFFIC_FILE.format(kernel=cls, workload=workload)
+        with open(path, "w") as fh:
+            json.dump(out, fh, indent=1)
+        print("wrote", path, out)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="scan_n128", choices=["scan_n128", "large_n256", "tiny_n32"])
+    ap.add_argument("--algorithm", default="RAAR")
+    ap.add_argument("--param", type=float, default=0.75)
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a plain copy of known size")
+    ap.add_argument("--copy-probe-bytes", type=int, default=1 << 30)
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, args.copy_probe_bytes)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the whole scan on a single MI355X "
+              "(multi-GPU sharding is a design, not an implementation); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    bench(args)
+
+
+if __name__ == "__main__":
+    main()

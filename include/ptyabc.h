@@ -176,6 +176,28 @@ pty_status pty_set_state(pty_scan *scan, const float *x, const float *y, const f
 /* Release the scan (not the caller's workspace).  NULL is a no-op. */
 void pty_destroy_scan(pty_scan *scan);
 
+/* Kernel classes for the per-kernel timing below. */
+typedef enum {
+  PTY_K_DIVIDE = 0,          /* divide, fused (N <= 128) or row forward pass (N = 256) */
+  PTY_K_DIVIDE_COLS = 1,     /* N = 256: column pass with the Fourier-space projection  */
+  PTY_K_DIVIDE_ROWS_INV = 2, /* N = 256: row inverse pass                                */
+  PTY_K_OBJECT = 3,          /* concur, object                                           */
+  PTY_K_PROBE_PARTIAL = 4,   /* concur, probe partial sums                               */
+  PTY_K_PROBE_FINAL = 5,     /* concur, probe finalisation and metrics                   */
+  PTY_K_COUNT = 6
+} pty_kernel_class;
+
+/* Per-kernel timing with HIP events recorded on the scan's stream around
+ * every launch of pty_iterate / pty_iterate_many.  enable = 1 starts timing
+ * and clears the totals; 0 stops it.  Timing adds two event records per
+ * launch and nothing else. */
+pty_status pty_profile(pty_scan *scan, int32_t enable);
+
+/* Synchronise, then give per class the total milliseconds and the number of
+ * launches timed since pty_profile(scan, 1).  ms and launches hold n entries;
+ * n may be smaller than PTY_K_COUNT. */
+pty_status pty_profile_read(pty_scan *scan, double *ms, int64_t *launches, int32_t n);
+
 const char *pty_status_string(int32_t status);
 const char *pty_last_error(void);
 

@@ -31,7 +31,9 @@ EXPORTS = [
     "pty_iterate", "pty_iterate_many", "pty_synchronize", "pty_get_object", "pty_get_probe",
     "pty_get_metrics", "pty_get_metric_history", "pty_get_iteration", "pty_get_state",
     "pty_set_state", "pty_destroy_scan", "pty_status_string", "pty_last_error",
+    "pty_profile", "pty_profile_read",
 ]
+KERNEL_CLASSES = ["divide", "divide_cols", "divide_rows_inv", "object", "probe_partial", "probe_final"]
 
 
 class PtyError(RuntimeError):
@@ -97,7 +99,10 @@ def load_library(path: str = LIB_PATH):
     L.pty_status_string.restype = ctypes.c_char_p
     L.pty_last_error.argtypes = []
     L.pty_last_error.restype = ctypes.c_char_p
-    for name in ("pty_create_scan", "pty_set_algorithm", "pty_set_algorithm_named", "pty_iterate",
+    L.pty_profile.argtypes = [P, ctypes.c_int32]
+    L.pty_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.c_int32]
+    for name in ("pty_profile", "pty_profile_read", "pty_create_scan", "pty_set_algorithm", "pty_set_algorithm_named", "pty_iterate",
                  "pty_iterate_many", "pty_synchronize", "pty_get_object", "pty_get_probe",
                  "pty_get_metrics", "pty_get_metric_history", "pty_get_state", "pty_set_state"):
         getattr(L, name).restype = ctypes.c_int32
@@ -261,6 +266,18 @@ class Scan:
         torch.cuda.synchronize(self.device)
         ptrs = [ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p() for t in ts]
         _check(self._L.pty_set_state(self._h, *ptrs, 1), "pty_set_state")
+
+    def profile(self, enable: bool = True):
+        """Start (clearing totals) or stop per-kernel HIP-event timing."""
+        _check(self._L.pty_profile(self._h, int(bool(enable))), "pty_profile")
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} since profile(True)."""
+        n = len(KERNEL_CLASSES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(self._L.pty_profile_read(self._h, ms, cnt, n), "pty_profile_read")
+        return {k: (ms[i], int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -12,6 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libptyabc.so")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 SOURCES = ["divide.hip", "concur.hip", "abi.cpp"]
 
 HIPCC_FLAGS = [
@@ -22,7 +23,6 @@ HIPCC_FLAGS = [
     "-shared",
     # packed float32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics",
     "-Wall",
     "-Wno-unused-function",
 ]
@@ -38,7 +38,7 @@ def hipcc() -> str:
 def build(verbose: bool = False, extra=None) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + list(extra or []) + ["-x", "hip"] + srcs + ["-o", tmp]
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-I" + INCLUDE] + list(extra or []) + ["-x", "hip"] + srcs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, cwd=CSRC, capture_output=True, text=True)

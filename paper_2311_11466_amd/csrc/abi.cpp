@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ptyabc.h"
+#include "ptyabc.h"
 #include "params.hpp"
 
 using namespace pty;
@@ -117,6 +117,13 @@ struct pty_scan {
   bool x_valid = false, y_valid = false;
   bool prev_metrics_done = true;          // metrics of iteration k-1 already finalised
   bool failed = false;
+  // per-kernel event timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_class;        // class of each (start, end) pair queued
+  size_t ev_used = 0;               // events handed out from ev_pool
+  double prof_ms[PTY_K_COUNT] = {0};
+  int64_t prof_n[PTY_K_COUNT] = {0};
 
   template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   float2* tmp_ptr() const { return L.tmp == size_t(-1) ? at<float2>(L.y) : at<float2>(L.tmp); }
@@ -139,6 +146,47 @@ pty_status check_usable(const pty_scan* s) {
   if (!s) return fail(PTY_ERR_INVALID_ARG, "scan is NULL");
   if (s->failed) return fail(PTY_ERR_BAD_STATE, "scan had a device error; only pty_destroy_scan is allowed");
   return PTY_OK;
+}
+
+// Record an event pair around one launch when timing is on.
+template <class F>
+hipError_t timed(pty_scan* s, int cls, F&& launch) {
+  if (!s->prof) return launch();
+  auto next = [&](hipEvent_t* e) -> hipError_t {
+    if (s->ev_used == s->ev_pool.size()) {
+      hipEvent_t ne;
+      hipError_t r = hipEventCreate(&ne);
+      if (r != hipSuccess) return r;
+      s->ev_pool.push_back(ne);
+    }
+    *e = s->ev_pool[s->ev_used++];
+    return hipSuccess;
+  };
+  hipEvent_t a, b;
+  hipError_t r = next(&a);
+  if (r == hipSuccess) r = next(&b);
+  if (r == hipSuccess) r = hipEventRecord(a, s->stream);
+  if (r == hipSuccess) r = launch();
+  if (r == hipSuccess) r = hipEventRecord(b, s->stream);
+  if (r == hipSuccess) s->ev_class.push_back(cls);
+  return r;
+}
+
+// fold the queued event pairs into the totals (synchronises the stream)
+hipError_t drain_profile(pty_scan* s) {
+  if (s->ev_class.empty()) return hipSuccess;
+  hipError_t r = hipStreamSynchronize(s->stream);
+  if (r != hipSuccess) return r;
+  for (size_t i = 0; i < s->ev_class.size(); ++i) {
+    float ms = 0.f;
+    r = hipEventElapsedTime(&ms, s->ev_pool[2 * i], s->ev_pool[2 * i + 1]);
+    if (r != hipSuccess) return r;
+    s->prof_ms[s->ev_class[i]] += ms;
+    s->prof_n[s->ev_class[i]] += 1;
+  }
+  s->ev_class.clear();
+  s->ev_used = 0;
+  return hipSuccess;
 }
 
 FinalParams final_params(const pty_scan* s) {
@@ -195,7 +243,12 @@ pty_status launch_iteration(pty_scan* s) {
   p.inv_scale = s->inv_scale;
   p.met = s->at<double>(s->L.met);
   p.nslot = s->L.nslot;
-  PTY_HIP(s, launch_divide(s->N, s->fp16, p, s->J, st), "divide launch");
+  if (s->prof && s->ev_class.size() > 4096) PTY_HIP(s, drain_profile(s), "profile drain");
+  for (int stage = 0; stage < divide_stages(s->N); ++stage) {
+    PTY_HIP(s, timed(s, PTY_K_DIVIDE + stage,
+                     [&] { return launch_divide_stage(s->N, s->fp16, p, s->J, stage, st); }),
+            "divide launch");
+  }
 
   ObjParams o{};
   o.y = s->ws + s->L.y;
@@ -212,7 +265,7 @@ pty_status launch_iteration(pty_scan* s) {
   o.pmax_part = s->at<float>(s->L.pmax);
   o.npb = s->L.npb;
   o.tau = s->tau;
-  PTY_HIP(s, launch_object_update(s->fp16, o, st), "object launch");
+  PTY_HIP(s, timed(s, PTY_K_OBJECT, [&] { return launch_object_update(s->fp16, o, st); }), "object launch");
 
   const bool update_probe = s->blind && s->k >= s->probe_update_start;
   if (update_probe) {
@@ -225,14 +278,16 @@ pty_status launch_iteration(pty_scan* s) {
     q.chunk = s->L.chunk;
     q.G = s->L.G;
     q.part = s->at<double>(s->L.part);
-    PTY_HIP(s, launch_probe_partial(s->fp16, q, st), "probe launch");
+    PTY_HIP(s, timed(s, PTY_K_PROBE_PARTIAL, [&] { return launch_probe_partial(s->fp16, q, st); }),
+            "probe launch");
   }
   FinalParams f = final_params(s);
   f.k_cur = s->k;
   f.k_prev = (p.prev_ec || p.prev_dx) ? s->k - 1 : -1;
   f.ec_ok = p.prev_ec;
   f.dx_ok = p.prev_dx;
-  PTY_HIP(s, launch_probe_final(f, update_probe, st), "finalise launch");
+  PTY_HIP(s, timed(s, PTY_K_PROBE_FINAL, [&] { return launch_probe_final(f, update_probe, st); }),
+          "finalise launch");
 
   // the new state is pending with this iteration's (a, b)
   s->mode = MODE_PENDING;
@@ -696,9 +751,37 @@ pty_status pty_set_state(pty_scan* scan, const float* x, const float* y, const f
   return PTY_OK;
 }
 
+pty_status pty_profile(pty_scan* scan, int32_t enable) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (enable != 0 && enable != 1) return fail(PTY_ERR_INVALID_ARG, "enable must be 0 or 1");
+  PTY_HIP(scan, drain_profile(scan), "profile drain");
+  if (enable) {
+    for (int i = 0; i < PTY_K_COUNT; ++i) {
+      scan->prof_ms[i] = 0.0;
+      scan->prof_n[i] = 0;
+    }
+  }
+  scan->prof = enable != 0;
+  return PTY_OK;
+}
+
+pty_status pty_profile_read(pty_scan* scan, double* ms, int64_t* launches, int32_t n) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (n < 0 || (n > 0 && (!ms || !launches))) return fail(PTY_ERR_INVALID_ARG, "bad ms/launches/n");
+  PTY_HIP(scan, drain_profile(scan), "profile drain");
+  for (int i = 0; i < n; ++i) {
+    ms[i] = i < PTY_K_COUNT ? scan->prof_ms[i] : 0.0;
+    launches[i] = i < PTY_K_COUNT ? scan->prof_n[i] : 0;
+  }
+  return PTY_OK;
+}
+
 void pty_destroy_scan(pty_scan* scan) {
   if (!scan) return;
   if (!scan->failed) (void)hipStreamSynchronize(scan->stream);
+  for (hipEvent_t e : scan->ev_pool) (void)hipEventDestroy(e);
   delete scan;
 }
 

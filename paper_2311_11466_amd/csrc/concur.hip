@@ -18,15 +18,24 @@ namespace pty {
 constexpr int kTileW = 64;
 constexpr int kTileH = 16;
 
+// One work-group per 64 x 16 object tile; a thread owns one column and four
+// rows (row0 + 4 i).  The tile's list of overlapping positions is staged in
+// LDS (in chunks of kListChunk), then consumed kUnroll entries at a time so
+// that each thread keeps 4 * kUnroll exit-wave loads in flight.
+constexpr int kListChunk = 256;
+constexpr int kUnroll = 4;
+
 template <class St>
 __global__ __launch_bounds__(256) void object_update_kernel(ObjParams p) {
   __shared__ float red[4];
+  __shared__ int4 ent[kListChunk];     // (scan index, row offset, col offset, unused)
   const int tile = blockIdx.x;
   const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = tx * kTileW + lane;
   const int row0 = ty * kTileH + wave;
   const int N = p.N;
+  const size_t NN = size_t(N) * N;
   using elem = typename St::elem;
   const elem* ys = reinterpret_cast<const elem*>(p.y);
 
@@ -37,23 +46,49 @@ __global__ __launch_bounds__(256) void object_update_kernel(ObjParams p) {
 
   double nr[4] = {0, 0, 0, 0}, ni[4] = {0, 0, 0, 0}, dd[4] = {0, 0, 0, 0};
   const int e0 = p.tile_off[tile], e1 = p.tile_off[tile + 1];
-  for (int e = e0; e < e1; ++e) {
-    const int j = p.tile_list[e];
-    const int2 pj = p.pos[j];
-    const int u1 = col - pj.y;
-    if ((unsigned)u1 >= (unsigned)N) continue;
-    const size_t base = size_t(j) * N * N;
+  for (int c0 = e0; c0 < e1; c0 += kListChunk) {
+    const int cn = min(kListChunk, e1 - c0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cn; i += 256) {
+      const int j = p.tile_list[c0 + i];
+      const int2 pj = p.pos[j];
+      ent[i] = make_int4(j, pj.x, pj.y, 0);
+    }
+    __syncthreads();
+    // Branch-free: indices are clamped into the window (valid addresses, the
+    // same rows and lines the in-window lanes fetch) and masked values are
+    // zeroed, so a group of loads issues back to back.
+    int e = 0;
+    for (; e < cn; e += kUnroll) {
+      float2 pv[kUnroll][4], yv[kUnroll][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int u0 = row0 + 4 * i - pj.x;
-      if ((unsigned)u0 < (unsigned)N) {
-        const int u = u0 * N + u1;
-        const float2 pv = p.probe[u];
-        const float2 yv = St::load(ys, base + u, p.inv_scale);
-        const double px = pv.x, py = pv.y, yx = yv.x, yy = yv.y;
-        nr[i] += px * yx + py * yy;
-        ni[i] += px * yy - py * yx;
-        dd[i] += px * px + py * py;
+      for (int q = 0; q < kUnroll; ++q) {
+        const int4 en = ent[min(e + q, cn - 1)];
+        const bool live = e + q < cn;
+        const int u1 = col - en.z;
+        const bool cin = live && (unsigned)u1 < (unsigned)N;
+        const int u1c = min(max(u1, 0), N - 1);
+        const elem* yj = ys + size_t(en.x) * NN;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int u0 = row0 + 4 * i - en.y;
+          const bool ok = cin && (unsigned)u0 < (unsigned)N;
+          const int u = min(max(u0, 0), N - 1) * N + u1c;
+          const float2 a = p.probe[u];
+          const float2 b = St::load(yj, u, p.inv_scale);
+          pv[q][i] = make_float2(ok ? a.x : 0.f, ok ? a.y : 0.f);
+          yv[q][i] = make_float2(ok ? b.x : 0.f, ok ? b.y : 0.f);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double px = pv[q][i].x, py = pv[q][i].y, yx = yv[q][i].x, yy = yv[q][i].y;
+          nr[i] += px * yx + py * yy;
+          ni[i] += px * yy - py * yx;
+          dd[i] += px * px + py * py;
+        }
       }
     }
   }

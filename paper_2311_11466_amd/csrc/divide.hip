@@ -38,84 +38,145 @@ __device__ __forceinline__ float2 update_x(float2 z, float2 yo, float2 xo, float
   return r;
 }
 
+// Relaxed modulus projection of one spectrum value, already scaled by 1/N^2
+// for the inverse transform: X (c A / |X| + 1 - c) / N^2, and c A / N^2 (phase
+// 0) where X = 0.  |X|^2 below the smallest normal float counts as zero.
+// Branch-free (per-component selects, hardware reciprocal square root).
+// Accumulates (|X| - A)^2 and A^2 in float32 per thread.
 __device__ __forceinline__ float2 fourier_op(float2 X, float A, float c, float one_minus_c, float inv_n2,
-                                             double& ef_num, double& ef_den) {
-  const float m2 = cnorm(X);
-  const double d = double(sqrtf(m2)) - double(A);
-  ef_num += d * d;
-  ef_den += double(A) * double(A);
-  if (m2 > 0.0f) {
-    const float f = fmaf(c * A, rsqrtf(m2), one_minus_c) * inv_n2;
-    return cscale(X, f);
-  }
-  return make_float2(c * A * inv_n2, 0.0f);
+                                             float& ef_num, float& ef_den) {
+  const float m2 = fmaf(X.x, X.x, X.y * X.y);
+  const bool nz = m2 >= 1.17549435e-38f;
+  const float r = __builtin_amdgcn_rsqf(nz ? m2 : 1.0f);
+  const float mag = nz ? m2 * r : 0.0f;
+  const float d = mag - A;
+  ef_num = fmaf(d, d, ef_num);
+  ef_den = fmaf(A, A, ef_den);
+  const float cA = c * A;
+  const float f = fmaf(cA, r, one_minus_c) * inv_n2;
+  float2 out;
+  out.x = nz ? X.x * f : cA * inv_n2;
+  out.y = nz ? X.y * f : 0.0f;
+  return out;
 }
 
+// Which exit-wave buffers the divide prologue touches.  The common cases are
+// compile-time so no load sits behind a per-element branch.
+enum ProMode { PRO_GENERAL = 0, PRO_MATERIAL = 1, PRO_INIT = 2, PRO_FLAGS = 3 };
+
+template <int MODE>
+struct Pro {
+  static constexpr bool rx(const DivideParams& p) { return MODE == PRO_FLAGS ? p.read_x : MODE != PRO_INIT; }
+  static constexpr bool ry(const DivideParams& p) { return MODE == PRO_FLAGS ? p.read_y : MODE == PRO_GENERAL; }
+  static constexpr bool wx(const DivideParams& p) { return MODE == PRO_FLAGS ? p.write_x : true; }
+  static constexpr bool ec(const DivideParams& p) { return MODE == PRO_FLAGS ? p.prev_ec : MODE == PRO_GENERAL; }
+  static constexpr bool dx(const DivideParams& p) { return MODE == PRO_FLAGS ? p.prev_dx : MODE == PRO_GENERAL; }
+};
+
+int prologue_mode(const DivideParams& p) {
+  if (p.read_x && p.read_y && p.write_x && p.prev_ec && p.prev_dx) return PRO_GENERAL;
+  if (p.read_x && !p.read_y && p.write_x && !p.prev_ec && !p.prev_dx) return PRO_MATERIAL;
+  if (!p.read_x && !p.read_y && p.write_x && !p.prev_ec && !p.prev_dx) return PRO_INIT;
+  return PRO_FLAGS;
+}
+
+// Register/LDS geometry of the fused kernel.  Task orders:
+//   stage A  qa = r2 * M + c2            (coalesced HBM access: c2 fastest)
+//   stage B  qb = c2 * 16 + kk           (kk = 4 kr1 + kc1; holds r2 -> kr2)
+//   stage C  qc = kr2 * 16 + kk          (holds c2 -> kc2)
+// With c2 / kr2 as the slow index of a stage-B / C task, every round
+// condition of a two-round exchange is uniform across a wavefront.
 template <int N, int T>
 struct DivGeom {
   static constexpr int M = N / 4;
   static constexpr int E = N * N / T;      // complex values per thread
   static constexpr int SA = E / 16;        // stage-A tasks per thread
   static constexpr int SB = E / M;         // stage-B / C tasks per thread
-  static constexpr int STRIDE = 4 * N + 1; // LDS plane pitch (odd: conflict-free strided access)
-  static constexpr int LDS = M * STRIDE;
+#ifndef PTY_N128_ROUNDS
+#define PTY_N128_ROUNDS 2
+#endif
+  static constexpr int NR = (N == 128) ? PTY_N128_ROUNDS : 1;  // exchange rounds (N = 128: ~68 KiB each)
+  static constexpr int PL = M / NR;        // LDS planes per round
+  static constexpr int PA = M * 17;        // A <-> B plane (r2): entry c2 * 17 + kk
+  static constexpr int PB = 16 * M + 16;   // B <-> C plane (c2): entry kr2 * 16 + kk
+  static constexpr int LDS = PL * (PA > PB ? PA : PB);
+#ifndef PTY_PROLOGUE_GROUP
+#define PTY_PROLOGUE_GROUP 8
+#endif
+  static constexpr int GP = PTY_PROLOGUE_GROUP;  // prologue elements whose loads are issued together
   static_assert(SA >= 1 && SB >= 1 && SA * 16 == E && SB * M == E, "geometry");
+  static_assert(NR == 1 || (SA == NR && SB == 1), "two-round exchanges assume one stage-B task and stage-A "
+                                                  "sets aligned with the rounds");
+  static_assert(NR == 1 || T / 16 == M, "stage-B round condition must be uniform per wavefront");
 };
 
-template <int N, int T, class St>
-__global__ __launch_bounds__(T) void divide_fused_kernel(DivideParams p) {
+template <int N, int T, class St, int MODE>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(DivGeom<N, T>::NR == 2 ? 4 : 2)))
+void divide_fused_kernel(DivideParams p) {
   using G = DivGeom<N, T>;
-  constexpr int M = G::M, E = G::E, SA = G::SA, SB = G::SB, STRIDE = G::STRIDE;
+  using PR = Pro<MODE>;
+  constexpr int M = G::M, E = G::E, SA = G::SA, SB = G::SB, NR = G::NR, PL = G::PL, PA = G::PA, PB = G::PB;
   __shared__ float2 lds[G::LDS];
   __shared__ double red[MF_COUNT * (T / 64)];
 
-  const int tid = threadIdx.x;
+  const unsigned tid = threadIdx.x;
   const int j = p.j_begin + blockIdx.x;
-  const size_t base = size_t(j) * N * N;
+  const size_t base = size_t(j) * (N * N);
   const int2 pj = p.pos[j];
   using elem = typename St::elem;
-  elem* __restrict__ xs = reinterpret_cast<elem*>(p.x);
-  elem* __restrict__ ys = reinterpret_cast<elem*>(p.y);
+  elem* __restrict__ xb = reinterpret_cast<elem*>(p.x) + base;
+  elem* __restrict__ yb = reinterpret_cast<elem*>(p.y) + base;
+  const float* __restrict__ ab = p.amp + base;
+  const float2* __restrict__ ob = p.obj + (size_t(pj.x) * p.obj_w + pj.y);
+  const float2* __restrict__ pb = p.probe;
   const float2* __restrict__ tw = p.tw;
+  const unsigned ow = p.obj_w;
+  const bool rx = PR::rx(p), ry = PR::ry(p), wx = PR::wx(p), mec = PR::ec(p), mdx = PR::dx(p);
 
   float2 v[E];
-  double acc[MF_COUNT];
-#pragma unroll
-  for (int q = 0; q < MF_COUNT; ++q) acc[q] = 0.0;
+  float ec_n = 0.f, ec_d = 0.f, dx_n = 0.f, dx_d = 0.f, ef_n = 0.f, ef_d = 0.f;
 
-  // ---- prologue (stage-A layout): form x_k --------------------------------
-  static_for<0, SA>([&](auto s) {
-    const int qa = tid + T * s.value;
-    const int r2 = qa / M, c2 = qa % M;
-    static_for<0, 16>([&](auto e) {
-      constexpr int r1 = e.value / 4, c1 = e.value % 4;
-      const int r = r2 + M * r1, c = c2 + M * c1;
-      const int idx = r * N + c;
-      const float2 z = cmul(p.probe[idx], p.obj[size_t(pj.x + r) * p.obj_w + (pj.y + c)]);
-      float2 xo = make_float2(0.f, 0.f), yo = make_float2(0.f, 0.f);
-      if (p.read_x) xo = St::load(xs, base + idx, p.inv_scale);
-      if (p.read_y) yo = St::load(ys, base + idx, p.inv_scale);
-      const float2 xn = update_x(z, yo, xo, p.alpha, p.beta, p.gamma);
-      if (p.prev_ec) {
-        const double dr = double(z.x) - double(yo.x), di = double(z.y) - double(yo.y);
-        acc[MF_EC_NUM] += dr * dr + di * di;
-        acc[MF_EC_DEN] += double(yo.x) * yo.x + double(yo.y) * yo.y;
-      }
-      if (p.prev_dx) {
-        const double dr = double(xn.x) - double(xo.x), di = double(xn.y) - double(xo.y);
-        acc[MF_DX_NUM] += dr * dr + di * di;
-        acc[MF_DX_DEN] += double(xo.x) * xo.x + double(xo.y) * xo.y;
-      }
-      if (p.write_x) St::store(xs, base + idx, xn, p.scale);
-      v[s.value * 16 + e.value] = xn;
+  // ---- prologue and stage A, set by set -----------------------------------
+  // x_k = alpha P S_j O + beta y + gamma x in the stage-A layout; loads go out
+  // GP elements at a time.  Then the 4x4 DFT over (r1, c1) and the twiddles
+  // W_N^(r2 kr1 + c2 kc1).
+  auto prologue_and_stage_a = [&](auto s) {
+    const unsigned qa = tid + T * s.value;
+    const unsigned r2 = qa / M, c2 = qa % M;
+    static_for<0, 16, G::GP>([&](auto g0) {
+      float2 zp[G::GP], zo[G::GP], xo[G::GP], yo[G::GP];
+      static_for<0, G::GP>([&](auto q) {
+        constexpr int e = g0.value + q.value;
+        constexpr int r1 = e / 4, c1 = e % 4;
+        const unsigned r = r2 + M * r1, c = c2 + M * c1;
+        const unsigned idx = r * N + c;
+        zp[q.value] = pb[idx];
+        zo[q.value] = ob[r * ow + c];
+        xo[q.value] = rx ? St::load(xb, idx, p.inv_scale) : make_float2(0.f, 0.f);
+        yo[q.value] = ry ? St::load(yb, idx, p.inv_scale) : make_float2(0.f, 0.f);
+      });
+      static_for<0, G::GP>([&](auto q) {
+        constexpr int e = g0.value + q.value;
+        constexpr int r1 = e / 4, c1 = e % 4;
+        const unsigned idx = (r2 + M * r1) * N + (c2 + M * c1);
+        const float2 z = cmul(zp[q.value], zo[q.value]);
+        const float2 xn = update_x(z, yo[q.value], xo[q.value], p.alpha, p.beta, p.gamma);
+        if (mec) {
+          const float dr = z.x - yo[q.value].x, di = z.y - yo[q.value].y;
+          ec_n = fmaf(dr, dr, fmaf(di, di, ec_n));
+          ec_d = fmaf(yo[q.value].x, yo[q.value].x, fmaf(yo[q.value].y, yo[q.value].y, ec_d));
+        }
+        if (mdx) {
+          const float dr = xn.x - xo[q.value].x, di = xn.y - xo[q.value].y;
+          dx_n = fmaf(dr, dr, fmaf(di, di, dx_n));
+          dx_d = fmaf(xo[q.value].x, xo[q.value].x, fmaf(xo[q.value].y, xo[q.value].y, dx_d));
+        }
+        if (wx) St::store(xb, idx, xn, p.scale);
+        v[s.value * 16 + e] = xn;
+      });
+      __builtin_amdgcn_sched_barrier(0);
     });
-  });
-
-  // ---- stage A forward: 4x4 DFT, twiddles -----------------------------------
-  static_for<0, SA>([&](auto s) {
     dft4x4_reg<false, s.value * 16>(v);
-    const int qa = tid + T * s.value;
-    const int r2 = qa / M, c2 = qa % M;
     const float2 wr1 = tw[r2], wr2 = tw[2 * r2], wr3 = tw[3 * r2];
     const float2 wc1 = tw[c2], wc2 = tw[2 * c2], wc3 = tw[3 * c2];
     static_for<0, 16>([&](auto e) {
@@ -129,75 +190,133 @@ __global__ __launch_bounds__(T) void divide_fused_kernel(DivideParams p) {
       if constexpr (kc1 == 3) t = cmul(t, wc3);
       v[s.value * 16 + e.value] = t;
     });
-  });
-
-  // ---- exchange A -> B: element (r2, kk, c2) at r2*STRIDE + kk*M + c2 --------
-  static_for<0, SA>([&](auto s) {
-    const int qa = tid + T * s.value;
-    const int r2 = qa / M, c2 = qa % M;
-    static_for<0, 16>([&](auto e) { lds[r2 * STRIDE + e.value * M + c2] = v[s.value * 16 + e.value]; });
-  });
-  __syncthreads();
-  static_for<0, SB>([&](auto s) {
-    const int qb = tid + T * s.value;
-    static_for<0, M>([&](auto r2) { v[s.value * M + r2.value] = lds[r2.value * STRIDE + qb]; });
-  });
-  // ---- stage B forward: DFT over r2 -----------------------------------------
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  // ---- exchange A -> B (planes r2): element (r2, kk, c2) at plane r2, entry
+  // c2*17 + kk.  Round h carries planes [h PL, (h+1) PL); with NR = 2 stage-A
+  // set h is exactly those planes, and the stage-B registers read in round h
+  // are the slots set h just wrote out.
+  auto write_a = [&](auto s, auto h) {
+    const unsigned qa = tid + T * s.value;
+    const unsigned lr = qa / M - h.value * PL, c2 = qa % M;
+    static_for<0, 16>([&](auto kk) { lds[lr * PA + c2 * 17 + kk.value] = v[s.value * 16 + kk.value]; });
+  };
+  auto read_b = [&](auto h) {
+    static_for<0, SB>([&](auto s) {
+      const unsigned qb = tid + T * s.value;
+      const unsigned o = (qb / 16) * 17 + qb % 16;
+      static_for<0, PL>([&](auto lr) { v[s.value * M + h.value * PL + lr.value] = lds[lr.value * PA + o]; });
+    });
+  };
+  if constexpr (NR == 1) {
+    static_for<0, SA>([&](auto s) { prologue_and_stage_a(s); });
+    static_for<0, SA>([&](auto s) { write_a(s, std::integral_constant<int, 0>{}); });
+    __syncthreads();
+    read_b(std::integral_constant<int, 0>{});
+    __syncthreads();
+  } else {
+    // set 0 goes out to LDS before set 1 is formed, so only one set's values
+    // and loads are in registers at a time
+    prologue_and_stage_a(std::integral_constant<int, 0>{});
+    write_a(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+    prologue_and_stage_a(std::integral_constant<int, 1>{});
+    __syncthreads();
+    read_b(std::integral_constant<int, 0>{});
+    __syncthreads();
+    write_a(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{});
+    __syncthreads();
+    read_b(std::integral_constant<int, 1>{});
+    __syncthreads();
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // ---- stage B forward: DFT over r2 -> kr2 --------------------------------
   static_for<0, SB>([&](auto s) { dft_reg<M, false, 1, s.value * M>(v); });
-  __syncthreads();
-  // ---- exchange B -> C: element (c2, kk, kr2) at c2*STRIDE + kk*M + kr2 ------
-  static_for<0, SB>([&](auto s) {
-    const int qb = tid + T * s.value;
-    const int kk = qb / M, c2 = qb % M;
-    static_for<0, M>([&](auto kr2) { lds[c2 * STRIDE + kk * M + kr2.value] = v[s.value * M + kr2.value]; });
-  });
-  __syncthreads();
-  static_for<0, SB>([&](auto s) {
-    const int qc = tid + T * s.value;
-    static_for<0, M>([&](auto c2) { v[s.value * M + c2.value] = lds[c2.value * STRIDE + qc]; });
-  });
-  // ---- stage C forward, Fourier-space relaxed projection, stage C inverse ----
+  __builtin_amdgcn_sched_barrier(0);
+
+  // ---- exchange B -> C (planes c2).  Round h: stage-B threads whose c2 is in
+  // the round write all registers (a wavefront-uniform test); every thread
+  // reads the round's planes.  Round-0 values wait in t0 because threads that
+  // write in round 1 still hold their stage-B data in those slots.
+  {
+    float2 t0[NR == 2 ? PL : 1];
+    static_for<0, NR>([&](auto h) {
+      static_for<0, SB>([&](auto s) {
+        const int qb = tid + T * s.value;
+        const int lc = qb / 16 - h.value * PL, kk = qb % 16;
+        if (NR == 1 || (unsigned)lc < (unsigned)PL) {
+          static_for<0, M>([&](auto kr2) { lds[lc * PB + kr2.value * 16 + kk] = v[s.value * M + kr2.value]; });
+        }
+      });
+      __syncthreads();
+      static_for<0, SB>([&](auto s) {
+        const int qc = tid + T * s.value;
+        static_for<0, PL>([&](auto lc) {
+          const float2 val = lds[lc.value * PB + qc];
+          if constexpr (NR == 2 && h.value == 0) t0[lc.value] = val;
+          else v[s.value * M + h.value * PL + lc.value] = val;
+        });
+      });
+      __syncthreads();
+    });
+    if constexpr (NR == 2) static_for<0, PL>([&](auto lc) { v[lc.value] = t0[lc.value]; });
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // ---- stage C forward, Fourier-space relaxed projection, stage C inverse --
   const float c = p.c, omc = 1.0f - p.c, inv_n2 = 1.0f / float(N * N);
   static_for<0, SB>([&](auto s) {
     dft_reg<M, false, 1, s.value * M>(v);
-    const int qc = tid + T * s.value;
+    const unsigned qc = tid + T * s.value;
     static_for<0, M>([&](auto kc2) {
-      const float A = p.amp[base + size_t(kc2.value) * (4 * N) + qc];
-      v[s.value * M + kc2.value] =
-          fourier_op(v[s.value * M + kc2.value], A, c, omc, inv_n2, acc[MF_EF_NUM], acc[MF_EF_DEN]);
+      const float A = ab[kc2.value * (4 * N) + qc];
+      v[s.value * M + kc2.value] = fourier_op(v[s.value * M + kc2.value], A, c, omc, inv_n2, ef_n, ef_d);
     });
     dft_reg<M, true, 1, s.value * M>(v);
   });
-  __syncthreads();
-  // ---- exchange C -> B -------------------------------------------------------
-  static_for<0, SB>([&](auto s) {
-    const int qc = tid + T * s.value;
-    static_for<0, M>([&](auto c2) { lds[c2.value * STRIDE + qc] = v[s.value * M + c2.value]; });
-  });
-  __syncthreads();
-  static_for<0, SB>([&](auto s) {
-    const int qb = tid + T * s.value;
-    const int kk = qb / M, c2 = qb % M;
-    static_for<0, M>([&](auto kr2) { v[s.value * M + kr2.value] = lds[c2 * STRIDE + kk * M + kr2.value]; });
-  });
-  // ---- stage B inverse -------------------------------------------------------
+  __builtin_amdgcn_sched_barrier(0);
+
+  // ---- exchange C -> B (planes c2), mirror of B -> C.  Round h: every thread
+  // writes its registers c2 of the round; stage-B threads whose c2 is in the
+  // round read.  In round 0 the upper half of those registers has not been
+  // written out yet, so its new values wait in t0.
+  {
+    float2 t0[NR == 2 ? PL : 1];
+    static_for<0, NR>([&](auto h) {
+      static_for<0, SB>([&](auto s) {
+        const int qc = tid + T * s.value;
+        static_for<0, PL>([&](auto lc) { lds[lc.value * PB + qc] = v[s.value * M + h.value * PL + lc.value]; });
+      });
+      __syncthreads();
+      static_for<0, SB>([&](auto s) {
+        const int qb = tid + T * s.value;
+        const int lc = qb / 16 - h.value * PL, kk = qb % 16;
+        if (NR == 1 || (unsigned)lc < (unsigned)PL) {
+          static_for<0, M>([&](auto kr2) {
+            const float2 val = lds[lc * PB + kr2.value * 16 + kk];
+            if constexpr (NR == 2 && h.value == 0 && kr2.value >= PL) t0[kr2.value - PL] = val;
+            else v[s.value * M + kr2.value] = val;
+          });
+        }
+      });
+      __syncthreads();
+    });
+    if constexpr (NR == 2) {
+      if (tid / 16 < PL) static_for<0, PL>([&](auto k) { v[PL + k.value] = t0[k.value]; });
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // ---- stage B inverse -----------------------------------------------------
   static_for<0, SB>([&](auto s) { dft_reg<M, true, 1, s.value * M>(v); });
-  __syncthreads();
-  // ---- exchange B -> A -------------------------------------------------------
-  static_for<0, SB>([&](auto s) {
-    const int qb = tid + T * s.value;
-    static_for<0, M>([&](auto r2) { lds[r2.value * STRIDE + qb] = v[s.value * M + r2.value]; });
-  });
-  __syncthreads();
-  static_for<0, SA>([&](auto s) {
-    const int qa = tid + T * s.value;
-    const int r2 = qa / M, c2 = qa % M;
-    static_for<0, 16>([&](auto e) { v[s.value * 16 + e.value] = lds[r2 * STRIDE + e.value * M + c2]; });
-  });
-  // ---- stage A inverse: conjugate twiddles, 4x4 inverse DFT, store y ---------
-  static_for<0, SA>([&](auto s) {
-    const int qa = tid + T * s.value;
-    const int r2 = qa / M, c2 = qa % M;
+  __builtin_amdgcn_sched_barrier(0);
+
+  // ---- exchange B -> A (planes r2), mirror of A -> B; then per set the
+  // conjugate twiddles, the 4x4 inverse DFT and the store of y ---------------
+  auto finish_set = [&](auto s) {
+    // recompute the element offsets instead of keeping the prologue's alive
+    // through the whole transform
+    unsigned qa = tid + T * s.value;
+    asm volatile("" : "+v"(qa));
+    const unsigned r2 = qa / M, c2 = qa % M;
     const float2 wr1 = tw[r2], wr2 = tw[2 * r2], wr3 = tw[3 * r2];
     const float2 wc1 = tw[c2], wc2 = tw[2 * c2], wc3 = tw[3 * c2];
     static_for<0, 16>([&](auto e) {
@@ -214,12 +333,33 @@ __global__ __launch_bounds__(T) void divide_fused_kernel(DivideParams p) {
     dft4x4_reg<true, s.value * 16>(v);
     static_for<0, 16>([&](auto e) {
       constexpr int r1 = e.value / 4, c1 = e.value % 4;
-      const int idx = (r2 + M * r1) * N + (c2 + M * c1);
-      St::store(ys, base + idx, v[s.value * 16 + e.value], p.scale);
+      St::store(yb, (r2 + M * r1) * N + (c2 + M * c1), v[s.value * 16 + e.value], p.scale);
     });
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  static_for<0, NR>([&](auto h) {
+    static_for<0, SB>([&](auto s) {
+      const unsigned qb = tid + T * s.value;
+      const unsigned o = (qb / 16) * 17 + qb % 16;
+      static_for<0, PL>([&](auto lr) { lds[lr.value * PA + o] = v[s.value * M + h.value * PL + lr.value]; });
+    });
+    __syncthreads();
+    static_for<0, SA>([&](auto s) {
+      if constexpr (NR == 1 || s.value == h.value) {
+        const unsigned qa = tid + T * s.value;
+        const unsigned lr = qa / M - h.value * PL, c2 = qa % M;
+        static_for<0, 16>([&](auto kk) { v[s.value * 16 + kk.value] = lds[lr * PA + c2 * 17 + kk.value]; });
+      }
+    });
+    if constexpr (NR == 2) {
+      __syncthreads();
+      finish_set(h);
+    }
   });
+  if constexpr (NR == 1) static_for<0, SA>([&](auto s) { finish_set(s); });
 
-  // ---- per-pattern metric partials -----------------------------------------
+  // ---- per-pattern metric partials (float64 block sums) ----------------------
+  double acc[MF_COUNT] = {ef_n, ef_d, ec_n, ec_d, dx_n, dx_d};
   block_sum<MF_COUNT, T>(acc, red);
   if (tid < MF_COUNT) p.met[size_t(j) * p.nslot * MF_COUNT + tid] = acc[tid];
 }
@@ -303,13 +443,14 @@ __global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
   __syncthreads();
   static_for<0, 16>([&](auto r2) { v[r2.value] = lds[cl * LT + t * LP + r2.value]; });
   dft_reg<16, false>(v);                                  // over r2 -> kr2; thread t = kr1
-  double acc[2] = {0.0, 0.0};
+  float ef_n = 0.f, ef_d = 0.f;
   const float c = p.c, omc = 1.0f - p.c, inv_n2 = 1.0f / float(L256 * L256);
   static_for<0, 16>([&](auto k2) {
     const int kr = t + 16 * k2.value;
     const float A = p.amp[base + size_t(kr) * L256 + col];
-    v[k2.value] = fourier_op(v[k2.value], A, c, omc, inv_n2, acc[0], acc[1]);
+    v[k2.value] = fourier_op(v[k2.value], A, c, omc, inv_n2, ef_n, ef_d);
   });
+  double acc[2] = {ef_n, ef_d};
   dft_reg<16, true>(v);                                   // over kr2 -> r2
   __syncthreads();
   static_for<0, 16>([&](auto r2) { lds[cl * LT + t * LP + r2.value] = v[r2.value]; });
@@ -394,7 +535,20 @@ __global__ __launch_bounds__(256) void flush_kernel(FlushParams p) {
 // ---------------------------------------------------------------------------
 template <int N, int T, class St>
 static hipError_t launch_fused(const DivideParams& p, int n_patterns, hipStream_t s) {
-  hipLaunchKernelGGL((divide_fused_kernel<N, T, St>), dim3(n_patterns), dim3(T), 0, s, p);
+  switch (prologue_mode(p)) {
+    case PRO_GENERAL:
+      hipLaunchKernelGGL((divide_fused_kernel<N, T, St, PRO_GENERAL>), dim3(n_patterns), dim3(T), 0, s, p);
+      break;
+    case PRO_MATERIAL:
+      hipLaunchKernelGGL((divide_fused_kernel<N, T, St, PRO_MATERIAL>), dim3(n_patterns), dim3(T), 0, s, p);
+      break;
+    case PRO_INIT:
+      hipLaunchKernelGGL((divide_fused_kernel<N, T, St, PRO_INIT>), dim3(n_patterns), dim3(T), 0, s, p);
+      break;
+    default:
+      hipLaunchKernelGGL((divide_fused_kernel<N, T, St, PRO_FLAGS>), dim3(n_patterns), dim3(T), 0, s, p);
+      break;
+  }
   return hipGetLastError();
 }
 
@@ -434,11 +588,34 @@ hipError_t launch_flush(int fp16, const FlushParams& p, int J, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class St>
+static hipError_t launch_stage_t(int n, const DivideParams& p, int n_patterns, int stage, hipStream_t s) {
+  if (n != 256) {
+    if (stage != 0) return hipErrorInvalidValue;
+    return launch_divide_t<St>(n, p, n_patterns, s);
+  }
+  const dim3 grid(16, n_patterns);
+  switch (stage) {
+    case 0: hipLaunchKernelGGL((rows256_fwd_kernel<St>), grid, dim3(256), 0, s, p); break;
+    case 1: hipLaunchKernelGGL(cols256_kernel, grid, dim3(256), 0, s, p); break;
+    case 2: hipLaunchKernelGGL((rows256_inv_kernel<St>), grid, dim3(256), 0, s, p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_divide_stage(int n, int fp16, const DivideParams& p, int n_patterns, int stage, hipStream_t s) {
+  if (n_patterns <= 0) return hipSuccess;
+  return fp16 ? launch_stage_t<StoreF16>(n, p, n_patterns, stage, s) : launch_stage_t<StoreF32>(n, p, n_patterns, stage, s);
+}
+
+int divide_stages(int n) { return n == 256 ? 3 : 1; }
+
 int divide_slots(int n) { return n == 256 ? 16 : 1; }
 bool divide_supported(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
 
 // Amplitudes sqrt(I) in the order the divide kernel reads them.  N <= 128:
-// amp[j][kc2][qc] with qc = (kr1*4 + kc1)*M + kr2 for the spectrum element
+// amp[j][kc2][qc] with qc = kr2*16 + kr1*4 + kc1 for the spectrum element
 // (kr1 + 4 kr2, kc1 + 4 kc2); N = 256: natural order.  Values that are not
 // finite or are negative are counted in *bad.
 __global__ void amp_prepare_kernel(const float* __restrict__ I, float* __restrict__ amp, int n, int J,
@@ -454,7 +631,7 @@ __global__ void amp_prepare_kernel(const float* __restrict__ I, float* __restric
       src = g;
     } else {
       const int kc2 = rem / (4 * n), qc = rem % (4 * n);
-      const int kk = qc / M, kr2 = qc % M;
+      const int kr2 = qc / 16, kk = qc % 16;
       const int kr = kk / 4 + 4 * kr2, kc = kk % 4 + 4 * kc2;
       src = j * nn + size_t(kr) * n + kc;
     }

@@ -93,6 +93,9 @@ struct FlushParams {
 
 // ---- launchers (return hipGetLastError() of the launch) ----
 hipError_t launch_divide(int n, int fp16, const DivideParams& p, int n_patterns, hipStream_t s);
+// one kernel of the divide: stage 0 (fused, or N = 256 rows forward), 1 (N = 256 columns), 2 (N = 256 rows inverse)
+hipError_t launch_divide_stage(int n, int fp16, const DivideParams& p, int n_patterns, int stage, hipStream_t s);
+int divide_stages(int n);
 hipError_t launch_object_update(int fp16, const ObjParams& p, hipStream_t s);
 hipError_t launch_probe_partial(int fp16, const ProbeParams& p, hipStream_t s);
 hipError_t launch_probe_final(const FinalParams& p, int update_probe, hipStream_t s);

@@ -113,14 +113,45 @@ def test_single_step_known_probe(cfg):
     assert np.array_equal(got[3], ref[0].probe.astype(np.complex64))
 
 
-@pytest.mark.parametrize("cfg,abc,n_iter,tol", [
-    ("tiny_n32", po.preset("RAAR", 0.75), 20, 1e-4),
-    ("tiny_n32", po.preset("DC"), 20, 1e-4),
-    ("p64", po.preset("RRR", 0.5), 10, 1e-4),
-    ("p256", po.preset("DR"), 5, 1e-4),
+def oracle_sensitivity(scan, abc, n_iter, seeds=(1, 2, 3), eps=1e-7):
+    """How far two oracle runs drift apart when the start differs by eps (relative).
+
+    A non-convex iteration amplifies differences; float32 rounding is such a
+    difference, so the GPU-vs-oracle bound of a free-running trajectory is
+    taken from the oracle's own amplification of a 1e-7 perturbation.
+    Returns per-quantity maxima over the seeds: x, obj (covered), probe, E_F.
+    """
+    amp = amp32(scan)
+    cov = covered_mask(scan)
+    base = po.init_state(scan.obj0.astype(np.complex64).astype(np.complex128),
+                         scan.probe0.astype(np.complex64).astype(np.complex128), scan.pos)
+    ref = po.run(base.copy(), amp, scan.pos, *abc, n_iter, blind=True)
+    worst = np.zeros(4)
+    for sd in seeds:
+        rng = np.random.default_rng(sd)
+        b = base.copy()
+        b.x = b.x * (1 + eps * rng.standard_normal(b.x.shape))
+        b = po.run(b, amp, scan.pos, *abc, n_iter, blind=True)
+        ef_a = np.array([m["fourier_err"] for m in ref.history])
+        ef_b = np.array([m["fourier_err"] for m in b.history])
+        d = [rel_l2(b.x, ref.x), rel_l2(b.obj, ref.obj, cov), rel_l2(b.probe, ref.probe),
+             float(np.max(np.abs(ef_a - ef_b) / ef_a))]
+        worst = np.maximum(worst, d)
+    return ref, worst
+
+
+@pytest.mark.parametrize("cfg,abc,n_iter", [
+    ("tiny_n32", po.preset("RAAR", 0.75), 20),
+    ("tiny_n32", po.preset("DC"), 20),
+    ("p64", po.preset("RRR", 0.5), 10),
+    ("p256", po.preset("DR"), 5),
 ])
-def test_trajectory(cfg, abc, n_iter, tol):
-    """Free-running iterations from the start: state and metric history."""
+def test_trajectory(cfg, abc, n_iter):
+    """Free-running iterations from the start: state and Fourier-error history.
+
+    Bound: 20 x the oracle's own drift under a 1e-7 start perturbation, and
+    never looser than needed: at least 1e-5.
+    """
     scan = get_scan(cfg)
     say("case: trajectory", cfg, abc, n_iter)
     g = gpu_scan(scan)
@@ -129,17 +160,16 @@ def test_trajectory(cfg, abc, n_iter, tol):
     x, y, o, p = (t.cpu().numpy() for t in g.get_state())
     hist = g.metric_history()
     g.close()
-    st = po.init_state(scan.obj0.astype(np.complex64).astype(np.complex128),
-                       scan.probe0.astype(np.complex64).astype(np.complex128), scan.pos)
-    st = po.run(st, amp32(scan), scan.pos, *abc, n_iter, blind=True)
+    ref, sens = oracle_sensitivity(scan, abc, n_iter)
+    tol = np.maximum(20 * sens, 1e-5)
     cov = covered_mask(scan)
-    errs = (rel_l2(x, st.x), rel_l2(o, st.obj, cov), rel_l2(p, st.probe))
-    say("  trajectory errors x/obj/probe", errs)
-    assert max(errs) <= tol
-    assert len(hist) == n_iter
-    for gm, om in zip(hist, st.history):
-        assert gm["iteration"] == om["iteration"]
-        assert abs(gm["fourier_err"] - om["fourier_err"]) <= 1e-3 * om["fourier_err"] + 1e-12
+    ef_g = np.array([m["fourier_err"] for m in hist])
+    ef_o = np.array([m["fourier_err"] for m in ref.history])
+    errs = np.array([rel_l2(x, ref.x), rel_l2(o, ref.obj, cov), rel_l2(p, ref.probe),
+                     float(np.max(np.abs(ef_g - ef_o) / ef_o))])
+    say("  gpu-vs-oracle x/obj/probe/E_F", errs, "oracle drift", sens)
+    assert np.all(errs <= tol), (errs, tol)
+    assert [m["iteration"] for m in hist] == list(range(n_iter))
 
 
 def test_fixed_point_noise_free():
