@@ -39,8 +39,8 @@ KERNEL_NAMES = {
     "divide_cols": "cols256_kernel",
     "divide_rows_inv": "rows256_inv_kernel",
     "object": "object_update_kernel",
-    "probe_partial": "probe_partial_kernel",
-    "probe_final": "probe_final_kernel",
+    "probe": "probe_partial_kernel",
+    "final": "probe_final_kernel",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{workload}.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_11466_amd", "csrc", f)
@@ -78,7 +78,7 @@ def algorithmic_bytes(kind: str, n: int, J: int, abc, blind: bool, storage: str,
         return (8 + 4 + 8) * nn
     if kind == "divide_rows_inv":
         return (8 + e) * nn
-    if kind in ("object", "probe_partial"):
+    if kind in ("object", "probe"):
         return e * nn
     return 0
 
@@ -205,6 +205,57 @@ def bench(args):
     print(json.dumps(line), flush=True)
 
 
+def _make_request(i):
+    """Worker: one request of the served mixed load (ptysynth recipe, seeded by i)."""
+    import numpy as np
+    from ptysynth import make_request, make_scan
+    from paper_2311_11466_amd.serve import request_from_scan
+    cfg, algo, prm = make_request(i)
+    sc = make_scan(cfg, intensity_dtype=np.float32)
+    return request_from_scan(i, sc, algo, prm, max_iter=200, tol=1e-3)
+
+
+def bench_served(args):
+    """Served mixed load: Poisson arrivals at a fraction of the closed-loop capacity."""
+    import multiprocessing as mp
+    import numpy as np
+    import torch
+    from paper_2311_11466_amd.serve import Server, poisson_arrivals
+    torch.cuda.set_device(0)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        reqs = pool.map(_make_request, range(args.requests))
+    print(f"# generated {len(reqs)} requests in {time.perf_counter() - t0:.1f} s on {workers} cores",
+          file=sys.stderr, flush=True)
+    warm = Server(budget_bytes=args.budget_gb * 1e9, max_slots=args.slots, chunk=10)
+    warm.run([reqs[0]])
+    for r in reqs:
+        r.arrival = 0.0
+    closed = Server(budget_bytes=args.budget_gb * 1e9, max_slots=args.slots, chunk=10).run(reqs)
+    capacity = len(reqs) / closed.wall
+    arr = poisson_arrivals(len(reqs), args.rate_factor * capacity, seed=501)
+    for r, t in zip(reqs, arr):
+        r.arrival = float(t)
+    opened = Server(budget_bytes=args.budget_gb * 1e9, max_slots=args.slots, chunk=10).run(reqs)
+    s = opened.summary()
+    line = {
+        "metric": "served mixed load: p50/p99 latency and aggregate projections/s at 1 GPU",
+        "value": round(s["projections_per_s"], 1), "unit": "projections/s", "n_gpus": 1,
+        "higher_is_better": True, "data": "synthetic",
+        "p50_latency_s": round(s["p50_latency_s"], 4), "p99_latency_s": round(s["p99_latency_s"], 4),
+        "closed_loop": {"requests_per_s": round(capacity, 3),
+                        "projections_per_s": round(closed.summary()["projections_per_s"], 1)},
+        "config": {"workload": "served", "requests": len(reqs), "arrival_rate_per_s": round(args.rate_factor * capacity, 3),
+                   "rate_factor": args.rate_factor, "budget_gb": args.budget_gb, "slots": args.slots,
+                   "chunk": 10, "max_iter": 200, "tol_fourier_err": 1e-3,
+                   "n_mix": {str(n): sum(r.n == n for r in reqs) for n in (64, 128, 256)},
+                   "peak_active": s["peak_active"], "peak_workspace_gb": round(s["peak_workspace_bytes"] / 1e9, 2)},
+        "iterations": [r.iterations for r in opened.results],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int):
     """Turn two rocprofv3 --pmc counter CSVs into the traffic file bench.py reads.
 
@@ -259,7 +310,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="scan_n128", choices=["scan_n128", "large_n256", "tiny_n32"])
+    ap.add_argument("--workload", default="scan_n128",
+                    choices=["scan_n128", "large_n256", "tiny_n32", "served"])
+    ap.add_argument("--requests", type=int, default=32, help="served: number of requests")
+    ap.add_argument("--rate-factor", type=float, default=0.7, help="served: arrival rate / closed-loop capacity")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="served: HBM budget")
+    ap.add_argument("--slots", type=int, default=32, help="served: concurrent scans")
     ap.add_argument("--algorithm", default="RAAR")
     ap.add_argument("--param", type=float, default=0.75)
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
@@ -275,7 +331,10 @@ def main():
         print("bench.py measures one GPU only: this build runs the whole scan on a single MI355X "
               "(multi-GPU sharding is a design, not an implementation); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    bench(args)
+    if args.workload == "served":
+        bench_served(args)
+    else:
+        bench(args)
 
 
 if __name__ == "__main__":

@@ -181,9 +181,9 @@ typedef enum {
   PTY_K_DIVIDE = 0,          /* divide, fused (N <= 128) or row forward pass (N = 256) */
   PTY_K_DIVIDE_COLS = 1,     /* N = 256: column pass with the Fourier-space projection  */
   PTY_K_DIVIDE_ROWS_INV = 2, /* N = 256: row inverse pass                                */
-  PTY_K_OBJECT = 3,          /* concur, object                                           */
-  PTY_K_PROBE_PARTIAL = 4,   /* concur, probe partial sums                               */
-  PTY_K_PROBE_FINAL = 5,     /* concur, probe finalisation and metrics                   */
+  PTY_K_OBJECT = 3,          /* concur, object (and the metric finalisation)             */
+  PTY_K_PROBE = 4,           /* concur, probe partial sums                               */
+  PTY_K_FINAL = 5,           /* probe finalisation and the metric history entry          */
   PTY_K_COUNT = 6
 } pty_kernel_class;
 

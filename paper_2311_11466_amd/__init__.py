@@ -33,7 +33,7 @@ EXPORTS = [
     "pty_set_state", "pty_destroy_scan", "pty_status_string", "pty_last_error",
     "pty_profile", "pty_profile_read",
 ]
-KERNEL_CLASSES = ["divide", "divide_cols", "divide_rows_inv", "object", "probe_partial", "probe_final"]
+KERNEL_CLASSES = ["divide", "divide_cols", "divide_rows_inv", "object", "probe", "final"]
 
 
 class PtyError(RuntimeError):

@@ -37,7 +37,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 enum Mode { MODE_INIT = 0, MODE_MATERIAL = 1, MODE_PENDING = 2 };
 
 struct Layout {
-  size_t amp, x, y, tmp, obj, probe, pos, tile_off, tile_list, part, met, ring, tile_max, pmax, tw, flag, total;
+  size_t amp, x, y, tmp, obj, probe, pos, tile_off, tile_list, part, met, met2, ring, tile_max, pmax, tw, flag,
+      total;
   int tiles_x, tiles_y, n_tiles, max_list, G, chunk, npb, nslot, cap;
   size_t elem_bytes;
 };
@@ -70,7 +71,8 @@ Layout make_layout(const pty_scan_desc* d) {
   const int per_pos = ((d->n + kTileH - 2) / kTileH + 1) * ((d->n + kTileW - 2) / kTileW + 1);
   L.max_list = int(J) * per_pos;
   L.npb = int((nn + 255) / 256);
-  int G = std::max(1, (2048 + L.npb - 1) / L.npb);
+  // position chunks of the probe reduction: about 1024 work-groups in all
+  int G = std::max(1, (1024 + L.npb - 1) / L.npb);
   G = std::min<int>(G, int(J));
   L.chunk = int((J + G - 1) / G);
   L.G = int((J + L.chunk - 1) / L.chunk);
@@ -90,6 +92,7 @@ Layout make_layout(const pty_scan_desc* d) {
   L.tile_list = take(size_t(L.max_list) * 4);
   L.part = take(3 * size_t(L.G) * nn * 8);
   L.met = take(J * size_t(L.nslot) * MF_COUNT * 8);
+  L.met2 = take(size_t(std::max(L.n_tiles, 64)) * MF_COUNT * 8);
   L.ring = take(size_t(L.cap) * kRingFields * 8);
   L.tile_max = take(size_t(L.n_tiles) * 4);
   L.pmax = take(size_t(L.npb) * 4);
@@ -189,7 +192,21 @@ hipError_t drain_profile(pty_scan* s) {
   return hipSuccess;
 }
 
-FinalParams final_params(const pty_scan* s) {
+MetricParams metric_params(const pty_scan* s, int slices) {
+  MetricParams m{};
+  m.met = s->at<double>(s->L.met);
+  m.J = s->J;
+  m.nslot = s->L.nslot;
+  m.part2 = s->at<double>(s->L.met2);
+  m.slices = slices;
+  m.ring = s->at<double>(s->L.ring);
+  m.cap = s->L.cap;
+  m.k_cur = -1;
+  m.k_prev = -1;
+  return m;
+}
+
+FinalParams final_params(const pty_scan* s, const MetricParams& mp) {
   FinalParams f{};
   f.part = s->at<double>(s->L.part);
   f.probe = s->at<float2>(s->L.probe);
@@ -200,17 +217,11 @@ FinalParams final_params(const pty_scan* s) {
   f.G = s->L.G;
   f.npb = s->L.npb;
   f.tau = s->tau;
-  f.met = s->at<double>(s->L.met);
-  f.J = s->J;
-  f.nslot = s->L.nslot;
-  f.ring = s->at<double>(s->L.ring);
-  f.cap = s->L.cap;
-  f.k_cur = -1;
-  f.k_prev = -1;
+  f.mp = mp;
   return f;
 }
 
-// One iteration: divide (with the pending update), object, [probe], finalise.
+// One iteration: divide (with the pending update), object (+ metrics), [probe].
 pty_status launch_iteration(pty_scan* s) {
   const hipStream_t st = s->stream;
   DivideParams p{};
@@ -265,6 +276,11 @@ pty_status launch_iteration(pty_scan* s) {
   o.pmax_part = s->at<float>(s->L.pmax);
   o.npb = s->L.npb;
   o.tau = s->tau;
+  o.mp = metric_params(s, s->L.n_tiles);
+  o.mp.k_cur = s->k;
+  o.mp.k_prev = (p.prev_ec || p.prev_dx) ? s->k - 1 : -1;
+  o.mp.ec_ok = p.prev_ec;
+  o.mp.dx_ok = p.prev_dx;
   PTY_HIP(s, timed(s, PTY_K_OBJECT, [&] { return launch_object_update(s->fp16, o, st); }), "object launch");
 
   const bool update_probe = s->blind && s->k >= s->probe_update_start;
@@ -278,16 +294,10 @@ pty_status launch_iteration(pty_scan* s) {
     q.chunk = s->L.chunk;
     q.G = s->L.G;
     q.part = s->at<double>(s->L.part);
-    PTY_HIP(s, timed(s, PTY_K_PROBE_PARTIAL, [&] { return launch_probe_partial(s->fp16, q, st); }),
-            "probe launch");
+    PTY_HIP(s, timed(s, PTY_K_PROBE, [&] { return launch_probe_partial(s->fp16, q, st); }), "probe launch");
   }
-  FinalParams f = final_params(s);
-  f.k_cur = s->k;
-  f.k_prev = (p.prev_ec || p.prev_dx) ? s->k - 1 : -1;
-  f.ec_ok = p.prev_ec;
-  f.dx_ok = p.prev_dx;
-  PTY_HIP(s, timed(s, PTY_K_PROBE_FINAL, [&] { return launch_probe_final(f, update_probe, st); }),
-          "finalise launch");
+  const FinalParams f = final_params(s, o.mp);
+  PTY_HIP(s, timed(s, PTY_K_FINAL, [&] { return launch_probe_final(f, update_probe, st); }), "finalise launch");
 
   // the new state is pending with this iteration's (a, b)
   s->mode = MODE_PENDING;
@@ -326,11 +336,12 @@ pty_status flush(pty_scan* s, bool materialise) {
   fp.nslot = s->L.nslot;
   PTY_HIP(s, launch_flush(s->fp16, fp, s->J, s->stream), "flush launch");
   if (want_metrics) {
-    FinalParams f = final_params(s);
-    f.k_prev = s->k - 1;
-    f.ec_ok = fp.read_y;
-    f.dx_ok = fp.read_x;
-    PTY_HIP(s, launch_metrics_only_final(f, s->stream), "metrics launch");
+    MetricParams m = metric_params(s, 1);
+    m.k_prev = s->k - 1;
+    m.ec_ok = fp.read_y;
+    m.dx_ok = fp.read_x;
+    PTY_HIP(s, launch_metric_slices(m, s->stream), "metrics launch");
+    PTY_HIP(s, launch_probe_final(final_params(s, m), 0, s->stream), "metrics launch");
     s->prev_metrics_done = true;
   }
   if (fp.write_x) {

@@ -9,7 +9,9 @@
 // its list in list order: every exit-wave pixel is read exactly once, no
 // atomics, and the result does not depend on launch order.
 // Probe: a grid of (256-pixel block) x (position chunk) writes float64
-// partial sums; a second kernel adds the chunks in ascending order.
+// partial sums; a finalise kernel adds the chunks in ascending order.  The
+// object launch also sums slices of the metric partials, which the finalise
+// kernel's last block adds up.
 #include "common.hpp"
 #include "params.hpp"
 
@@ -17,6 +19,54 @@ namespace pty {
 
 constexpr int kTileW = 64;
 constexpr int kTileH = 16;
+
+// Slice `b` of the metric partials, summed in a fixed order into part2[b].
+__device__ void metric_slice(const MetricParams& p, int b, double* red) {
+  double acc[MF_COUNT];
+#pragma unroll
+  for (int q = 0; q < MF_COUNT; ++q) acc[q] = 0.0;
+  const int total = p.J * p.nslot;
+  const int per = (total + p.slices - 1) / p.slices;
+  const int i0 = b * per, i1 = min(total, i0 + per);
+  for (int i = i0 + int(threadIdx.x); i < i1; i += 256) {
+#pragma unroll
+    for (int q = 0; q < MF_COUNT; ++q) acc[q] += p.met[size_t(i) * MF_COUNT + q];
+  }
+  block_sum<MF_COUNT, 256>(acc, red);
+  if (threadIdx.x < MF_COUNT) p.part2[size_t(b) * MF_COUNT + threadIdx.x] = acc[threadIdx.x];
+}
+
+// Add the slice sums in order and write the history ring (one work-group).
+__device__ void metric_finish(const MetricParams& p, double* red) {
+  double acc[MF_COUNT];
+#pragma unroll
+  for (int q = 0; q < MF_COUNT; ++q) acc[q] = 0.0;
+  for (int i = threadIdx.x; i < p.slices; i += 256) {
+#pragma unroll
+    for (int q = 0; q < MF_COUNT; ++q) acc[q] += p.part2[size_t(i) * MF_COUNT + q];
+  }
+  block_sum<MF_COUNT, 256>(acc, red);
+  if (threadIdx.x == 0) {
+    const double nan = __builtin_nan("");
+    if (p.k_cur >= 0) {
+      double* e = p.ring + (p.k_cur % p.cap) * kRingFields;
+      e[0] = double(p.k_cur);
+      e[1] = acc[MF_EF_DEN] > 0 ? acc[MF_EF_NUM] / acc[MF_EF_DEN] : nan;
+      e[2] = nan;
+      e[3] = nan;
+    }
+    if (p.k_prev >= 0) {
+      double* e = p.ring + (p.k_prev % p.cap) * kRingFields;
+      e[2] = (p.ec_ok && acc[MF_EC_DEN] > 0) ? acc[MF_EC_NUM] / acc[MF_EC_DEN] : nan;
+      e[3] = (p.dx_ok && acc[MF_DX_DEN] > 0) ? sqrt(acc[MF_DX_NUM] / acc[MF_DX_DEN]) : nan;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void metric_slice_kernel(MetricParams p) {
+  __shared__ double red[MF_COUNT * 4];
+  metric_slice(p, blockIdx.x, red);
+}
 
 // One work-group per 64 x 16 object tile; a thread owns one column and four
 // rows (row0 + 4 i).  The tile's list of overlapping positions is staged in
@@ -108,80 +158,51 @@ __global__ __launch_bounds__(256) void object_update_kernel(ObjParams p) {
   }
   m = block_max<256>(m, red);
   if (threadIdx.x == 0) p.tile_max[tile] = m;
+  __shared__ double mred[MF_COUNT * 4];
+  metric_slice(p.mp, tile, mred);
 }
+
+constexpr int kProbeUnroll = 8;
 
 template <class St>
 __global__ __launch_bounds__(256) void probe_partial_kernel(ProbeParams p) {
   const int N = p.N;
+  const int NN = N * N;
   const int u = blockIdx.x * 256 + threadIdx.x;
   const int g = blockIdx.y;
   const int j0 = g * p.chunk;
   const int j1 = min(p.J, j0 + p.chunk);
-  const int u0 = u / N, u1 = u % N;
+  const int uu = min(u, NN - 1);
+  const int u0 = uu / N, u1 = uu % N;
   using elem = typename St::elem;
   const elem* ys = reinterpret_cast<const elem*>(p.y);
   double nr = 0.0, ni = 0.0, dd = 0.0;
-  if (u < N * N) {
-    int j = j0;
-    // four positions per step so that eight loads are in flight per thread
-    for (; j + 4 <= j1; j += 4) {
-      float2 ov[4], yv[4];
+  // kProbeUnroll positions per step: 2 * kProbeUnroll loads in flight
+  for (int j = j0; j < j1; j += kProbeUnroll) {
+    float2 ov[kProbeUnroll], yv[kProbeUnroll];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int2 pj = p.pos[j + q];
-        ov[q] = p.obj[size_t(pj.x + u0) * p.W + (pj.y + u1)];
-        yv[q] = St::load(ys, size_t(j + q) * N * N + u, p.inv_scale);
-      }
+    for (int q = 0; q < kProbeUnroll; ++q) {
+      const int jj = min(j + q, j1 - 1);
+      const int2 pj = p.pos[jj];
+      ov[q] = p.obj[size_t(pj.x + u0) * p.W + (pj.y + u1)];
+      yv[q] = St::load(ys, size_t(jj) * NN + uu, p.inv_scale);
+    }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kProbeUnroll; ++q) {
+      if (j + q < j1) {
         const double ox = ov[q].x, oy = ov[q].y, yx = yv[q].x, yy = yv[q].y;
         nr += ox * yx + oy * yy;
         ni += ox * yy - oy * yx;
         dd += ox * ox + oy * oy;
       }
     }
-    for (; j < j1; ++j) {
-      const int2 pj = p.pos[j];
-      const float2 ov = p.obj[size_t(pj.x + u0) * p.W + (pj.y + u1)];
-      const float2 yv = St::load(ys, size_t(j) * N * N + u, p.inv_scale);
-      const double ox = ov.x, oy = ov.y, yx = yv.x, yy = yv.y;
-      nr += ox * yx + oy * yy;
-      ni += ox * yy - oy * yx;
-      dd += ox * ox + oy * oy;
-    }
-    const size_t plane = size_t(p.G) * N * N;
-    const size_t o = size_t(g) * N * N + u;
+  }
+  if (u < NN) {
+    const size_t plane = size_t(p.G) * NN;
+    const size_t o = size_t(g) * NN + u;
     p.part[o] = nr;
     p.part[plane + o] = ni;
     p.part[2 * plane + o] = dd;
-  }
-}
-
-// fixed-order metric reduction over [J][nslot][MF_COUNT]; one block
-__device__ void finalize_metrics(const FinalParams& p, double* red) {
-  double acc[MF_COUNT];
-#pragma unroll
-  for (int q = 0; q < MF_COUNT; ++q) acc[q] = 0.0;
-  const int total = p.J * p.nslot;
-  for (int i = threadIdx.x; i < total; i += 256) {
-#pragma unroll
-    for (int q = 0; q < MF_COUNT; ++q) acc[q] += p.met[size_t(i) * MF_COUNT + q];
-  }
-  block_sum<MF_COUNT, 256>(acc, red);
-  if (threadIdx.x == 0) {
-    const double nan = __builtin_nan("");
-    if (p.k_cur >= 0) {
-      double* e = p.ring + (p.k_cur % p.cap) * kRingFields;
-      e[0] = double(p.k_cur);
-      e[1] = acc[MF_EF_DEN] > 0 ? acc[MF_EF_NUM] / acc[MF_EF_DEN] : nan;
-      e[2] = nan;
-      e[3] = nan;
-    }
-    if (p.k_prev >= 0) {
-      double* e = p.ring + (p.k_prev % p.cap) * kRingFields;
-      e[2] = (p.ec_ok && acc[MF_EC_DEN] > 0) ? acc[MF_EC_NUM] / acc[MF_EC_DEN] : nan;
-      e[3] = (p.dx_ok && acc[MF_DX_DEN] > 0) ? sqrt(acc[MF_DX_NUM] / acc[MF_DX_DEN]) : nan;
-    }
   }
 }
 
@@ -190,7 +211,7 @@ __global__ __launch_bounds__(256) void probe_final_kernel(FinalParams p) {
   __shared__ float fred[4];
   const int b = blockIdx.x + p.first_block;
   if (b == p.npb) {
-    finalize_metrics(p, dred);
+    metric_finish(p.mp, dred);
     return;
   }
   const int NN = p.N * p.N;
@@ -203,7 +224,24 @@ __global__ __launch_bounds__(256) void probe_final_kernel(FinalParams p) {
   if (u < NN) {
     const size_t plane = size_t(p.G) * NN;
     double nr = 0.0, ni = 0.0, dd = 0.0;
-    for (int g = 0; g < p.G; ++g) {
+    int g = 0;
+    for (; g + 4 <= p.G; g += 4) {
+      double a[4], c[4], d[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const size_t o = size_t(g + q) * NN + u;
+        a[q] = p.part[o];
+        c[q] = p.part[plane + o];
+        d[q] = p.part[2 * plane + o];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        nr += a[q];
+        ni += c[q];
+        dd += d[q];
+      }
+    }
+    for (; g < p.G; ++g) {
       const size_t o = size_t(g) * NN + u;
       nr += p.part[o];
       ni += p.part[plane + o];
@@ -262,8 +300,9 @@ hipError_t launch_probe_final(const FinalParams& p, int update_probe, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_metrics_only_final(const FinalParams& p, hipStream_t s) {
-  return launch_probe_final(p, 0, s);
+hipError_t launch_metric_slices(const MetricParams& p, hipStream_t s) {
+  hipLaunchKernelGGL(metric_slice_kernel, dim3(p.slices), dim3(256), 0, s, p);
+  return hipGetLastError();
 }
 
 hipError_t launch_max_abs2_parts(const float2* a, size_t count, float* parts, int nparts, hipStream_t s) {

@@ -62,21 +62,25 @@ __device__ __forceinline__ float2 fourier_op(float2 X, float A, float c, float o
 
 // Which exit-wave buffers the divide prologue touches.  The common cases are
 // compile-time so no load sits behind a per-element branch.
-enum ProMode { PRO_GENERAL = 0, PRO_MATERIAL = 1, PRO_INIT = 2, PRO_FLAGS = 3 };
+enum ProMode { PRO_GENERAL = 0, PRO_UPDATE = 1, PRO_MATERIAL = 2, PRO_INIT = 3, PRO_FLAGS = 4 };
 
 template <int MODE>
 struct Pro {
   static constexpr bool rx(const DivideParams& p) { return MODE == PRO_FLAGS ? p.read_x : MODE != PRO_INIT; }
-  static constexpr bool ry(const DivideParams& p) { return MODE == PRO_FLAGS ? p.read_y : MODE == PRO_GENERAL; }
+  static constexpr bool ry(const DivideParams& p) {
+    return MODE == PRO_FLAGS ? p.read_y : (MODE == PRO_GENERAL || MODE == PRO_UPDATE);
+  }
   static constexpr bool wx(const DivideParams& p) { return MODE == PRO_FLAGS ? p.write_x : true; }
   static constexpr bool ec(const DivideParams& p) { return MODE == PRO_FLAGS ? p.prev_ec : MODE == PRO_GENERAL; }
   static constexpr bool dx(const DivideParams& p) { return MODE == PRO_FLAGS ? p.prev_dx : MODE == PRO_GENERAL; }
 };
 
 int prologue_mode(const DivideParams& p) {
+  const bool met = p.prev_ec || p.prev_dx;
   if (p.read_x && p.read_y && p.write_x && p.prev_ec && p.prev_dx) return PRO_GENERAL;
-  if (p.read_x && !p.read_y && p.write_x && !p.prev_ec && !p.prev_dx) return PRO_MATERIAL;
-  if (!p.read_x && !p.read_y && p.write_x && !p.prev_ec && !p.prev_dx) return PRO_INIT;
+  if (p.read_x && p.read_y && p.write_x && !met) return PRO_UPDATE;
+  if (p.read_x && !p.read_y && p.write_x && !met) return PRO_MATERIAL;
+  if (!p.read_x && !p.read_y && p.write_x && !met) return PRO_INIT;
   return PRO_FLAGS;
 }
 
@@ -84,38 +88,30 @@ int prologue_mode(const DivideParams& p) {
 //   stage A  qa = r2 * M + c2            (coalesced HBM access: c2 fastest)
 //   stage B  qb = c2 * 16 + kk           (kk = 4 kr1 + kc1; holds r2 -> kr2)
 //   stage C  qc = kr2 * 16 + kk          (holds c2 -> kc2)
-// With c2 / kr2 as the slow index of a stage-B / C task, every round
-// condition of a two-round exchange is uniform across a wavefront.
+// LDS entries are padded so the strided side of every exchange spreads over
+// the banks.
 template <int N, int T>
 struct DivGeom {
   static constexpr int M = N / 4;
   static constexpr int E = N * N / T;      // complex values per thread
   static constexpr int SA = E / 16;        // stage-A tasks per thread
   static constexpr int SB = E / M;         // stage-B / C tasks per thread
-#ifndef PTY_N128_ROUNDS
-#define PTY_N128_ROUNDS 2
-#endif
-  static constexpr int NR = (N == 128) ? PTY_N128_ROUNDS : 1;  // exchange rounds (N = 128: ~68 KiB each)
-  static constexpr int PL = M / NR;        // LDS planes per round
   static constexpr int PA = M * 17;        // A <-> B plane (r2): entry c2 * 17 + kk
-  static constexpr int PB = 16 * M + 16;   // B <-> C plane (c2): entry kr2 * 16 + kk
-  static constexpr int LDS = PL * (PA > PB ? PA : PB);
+  static constexpr int PB = 16 * M + 16;   // B <-> C plane (c2): entry kr2 * 16 + kk, padded
+  static constexpr int LDS = M * (PA > PB ? PA : PB);   // N = 128: 136 KiB, one pattern per CU
 #ifndef PTY_PROLOGUE_GROUP
 #define PTY_PROLOGUE_GROUP 8
 #endif
   static constexpr int GP = PTY_PROLOGUE_GROUP;  // prologue elements whose loads are issued together
   static_assert(SA >= 1 && SB >= 1 && SA * 16 == E && SB * M == E, "geometry");
-  static_assert(NR == 1 || (SA == NR && SB == 1), "two-round exchanges assume one stage-B task and stage-A "
-                                                  "sets aligned with the rounds");
-  static_assert(NR == 1 || T / 16 == M, "stage-B round condition must be uniform per wavefront");
 };
 
 template <int N, int T, class St, int MODE>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(DivGeom<N, T>::NR == 2 ? 4 : 2)))
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(2)))
 void divide_fused_kernel(DivideParams p) {
   using G = DivGeom<N, T>;
   using PR = Pro<MODE>;
-  constexpr int M = G::M, E = G::E, SA = G::SA, SB = G::SB, NR = G::NR, PL = G::PL, PA = G::PA, PB = G::PB;
+  constexpr int M = G::M, E = G::E, SA = G::SA, SB = G::SB, PA = G::PA, PB = G::PB;
   __shared__ float2 lds[G::LDS];
   __shared__ double red[MF_COUNT * (T / 64)];
 
@@ -192,74 +188,37 @@ void divide_fused_kernel(DivideParams p) {
     });
     __builtin_amdgcn_sched_barrier(0);
   };
-  // ---- exchange A -> B (planes r2): element (r2, kk, c2) at plane r2, entry
-  // c2*17 + kk.  Round h carries planes [h PL, (h+1) PL); with NR = 2 stage-A
-  // set h is exactly those planes, and the stage-B registers read in round h
-  // are the slots set h just wrote out.
-  auto write_a = [&](auto s, auto h) {
+  // ---- exchange A -> B: element (r2, kk, c2) at plane r2, entry c2*17 + kk --
+  static_for<0, SA>([&](auto s) { prologue_and_stage_a(s); });
+  static_for<0, SA>([&](auto s) {
     const unsigned qa = tid + T * s.value;
-    const unsigned lr = qa / M - h.value * PL, c2 = qa % M;
-    static_for<0, 16>([&](auto kk) { lds[lr * PA + c2 * 17 + kk.value] = v[s.value * 16 + kk.value]; });
-  };
-  auto read_b = [&](auto h) {
-    static_for<0, SB>([&](auto s) {
-      const unsigned qb = tid + T * s.value;
-      const unsigned o = (qb / 16) * 17 + qb % 16;
-      static_for<0, PL>([&](auto lr) { v[s.value * M + h.value * PL + lr.value] = lds[lr.value * PA + o]; });
-    });
-  };
-  if constexpr (NR == 1) {
-    static_for<0, SA>([&](auto s) { prologue_and_stage_a(s); });
-    static_for<0, SA>([&](auto s) { write_a(s, std::integral_constant<int, 0>{}); });
-    __syncthreads();
-    read_b(std::integral_constant<int, 0>{});
-    __syncthreads();
-  } else {
-    // set 0 goes out to LDS before set 1 is formed, so only one set's values
-    // and loads are in registers at a time
-    prologue_and_stage_a(std::integral_constant<int, 0>{});
-    write_a(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
-    prologue_and_stage_a(std::integral_constant<int, 1>{});
-    __syncthreads();
-    read_b(std::integral_constant<int, 0>{});
-    __syncthreads();
-    write_a(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{});
-    __syncthreads();
-    read_b(std::integral_constant<int, 1>{});
-    __syncthreads();
-  }
+    const unsigned r2 = qa / M, c2 = qa % M;
+    static_for<0, 16>([&](auto kk) { lds[r2 * PA + c2 * 17 + kk.value] = v[s.value * 16 + kk.value]; });
+  });
+  __syncthreads();
+  static_for<0, SB>([&](auto s) {
+    const unsigned qb = tid + T * s.value;
+    const unsigned o = (qb / 16) * 17 + qb % 16;
+    static_for<0, M>([&](auto r2) { v[s.value * M + r2.value] = lds[r2.value * PA + o]; });
+  });
+  __syncthreads();
   __builtin_amdgcn_sched_barrier(0);
   // ---- stage B forward: DFT over r2 -> kr2 --------------------------------
   static_for<0, SB>([&](auto s) { dft_reg<M, false, 1, s.value * M>(v); });
   __builtin_amdgcn_sched_barrier(0);
 
-  // ---- exchange B -> C (planes c2).  Round h: stage-B threads whose c2 is in
-  // the round write all registers (a wavefront-uniform test); every thread
-  // reads the round's planes.  Round-0 values wait in t0 because threads that
-  // write in round 1 still hold their stage-B data in those slots.
-  {
-    float2 t0[NR == 2 ? PL : 1];
-    static_for<0, NR>([&](auto h) {
-      static_for<0, SB>([&](auto s) {
-        const int qb = tid + T * s.value;
-        const int lc = qb / 16 - h.value * PL, kk = qb % 16;
-        if (NR == 1 || (unsigned)lc < (unsigned)PL) {
-          static_for<0, M>([&](auto kr2) { lds[lc * PB + kr2.value * 16 + kk] = v[s.value * M + kr2.value]; });
-        }
-      });
-      __syncthreads();
-      static_for<0, SB>([&](auto s) {
-        const int qc = tid + T * s.value;
-        static_for<0, PL>([&](auto lc) {
-          const float2 val = lds[lc.value * PB + qc];
-          if constexpr (NR == 2 && h.value == 0) t0[lc.value] = val;
-          else v[s.value * M + h.value * PL + lc.value] = val;
-        });
-      });
-      __syncthreads();
-    });
-    if constexpr (NR == 2) static_for<0, PL>([&](auto lc) { v[lc.value] = t0[lc.value]; });
-  }
+  // ---- exchange B -> C: element (c2, kk, kr2) at plane c2, entry kr2*16 + kk
+  static_for<0, SB>([&](auto s) {
+    const unsigned qb = tid + T * s.value;
+    const unsigned c2 = qb / 16, kk = qb % 16;
+    static_for<0, M>([&](auto k) { lds[c2 * PB + k.value * 16 + kk] = v[s.value * M + k.value]; });
+  });
+  __syncthreads();
+  static_for<0, SB>([&](auto s) {
+    const unsigned qc = tid + T * s.value;
+    static_for<0, M>([&](auto c) { v[s.value * M + c.value] = lds[c.value * PB + qc]; });
+  });
+  __syncthreads();
   __builtin_amdgcn_sched_barrier(0);
 
   // ---- stage C forward, Fourier-space relaxed projection, stage C inverse --
@@ -275,42 +234,25 @@ void divide_fused_kernel(DivideParams p) {
   });
   __builtin_amdgcn_sched_barrier(0);
 
-  // ---- exchange C -> B (planes c2), mirror of B -> C.  Round h: every thread
-  // writes its registers c2 of the round; stage-B threads whose c2 is in the
-  // round read.  In round 0 the upper half of those registers has not been
-  // written out yet, so its new values wait in t0.
-  {
-    float2 t0[NR == 2 ? PL : 1];
-    static_for<0, NR>([&](auto h) {
-      static_for<0, SB>([&](auto s) {
-        const int qc = tid + T * s.value;
-        static_for<0, PL>([&](auto lc) { lds[lc.value * PB + qc] = v[s.value * M + h.value * PL + lc.value]; });
-      });
-      __syncthreads();
-      static_for<0, SB>([&](auto s) {
-        const int qb = tid + T * s.value;
-        const int lc = qb / 16 - h.value * PL, kk = qb % 16;
-        if (NR == 1 || (unsigned)lc < (unsigned)PL) {
-          static_for<0, M>([&](auto kr2) {
-            const float2 val = lds[lc * PB + kr2.value * 16 + kk];
-            if constexpr (NR == 2 && h.value == 0 && kr2.value >= PL) t0[kr2.value - PL] = val;
-            else v[s.value * M + kr2.value] = val;
-          });
-        }
-      });
-      __syncthreads();
-    });
-    if constexpr (NR == 2) {
-      if (tid / 16 < PL) static_for<0, PL>([&](auto k) { v[PL + k.value] = t0[k.value]; });
-    }
-  }
+  // ---- exchange C -> B, mirror of B -> C ------------------------------------
+  static_for<0, SB>([&](auto s) {
+    const unsigned qc = tid + T * s.value;
+    static_for<0, M>([&](auto c) { lds[c.value * PB + qc] = v[s.value * M + c.value]; });
+  });
+  __syncthreads();
+  static_for<0, SB>([&](auto s) {
+    const unsigned qb = tid + T * s.value;
+    const unsigned c2 = qb / 16, kk = qb % 16;
+    static_for<0, M>([&](auto k) { v[s.value * M + k.value] = lds[c2 * PB + k.value * 16 + kk]; });
+  });
+  __syncthreads();
   __builtin_amdgcn_sched_barrier(0);
   // ---- stage B inverse -----------------------------------------------------
   static_for<0, SB>([&](auto s) { dft_reg<M, true, 1, s.value * M>(v); });
   __builtin_amdgcn_sched_barrier(0);
 
-  // ---- exchange B -> A (planes r2), mirror of A -> B; then per set the
-  // conjugate twiddles, the 4x4 inverse DFT and the store of y ---------------
+  // ---- exchange B -> A, mirror of A -> B; then per set the conjugate
+  // twiddles, the 4x4 inverse DFT and the store of y --------------------------
   auto finish_set = [&](auto s) {
     // recompute the element offsets instead of keeping the prologue's alive
     // through the whole transform
@@ -337,26 +279,18 @@ void divide_fused_kernel(DivideParams p) {
     });
     __builtin_amdgcn_sched_barrier(0);
   };
-  static_for<0, NR>([&](auto h) {
-    static_for<0, SB>([&](auto s) {
-      const unsigned qb = tid + T * s.value;
-      const unsigned o = (qb / 16) * 17 + qb % 16;
-      static_for<0, PL>([&](auto lr) { lds[lr.value * PA + o] = v[s.value * M + h.value * PL + lr.value]; });
-    });
-    __syncthreads();
-    static_for<0, SA>([&](auto s) {
-      if constexpr (NR == 1 || s.value == h.value) {
-        const unsigned qa = tid + T * s.value;
-        const unsigned lr = qa / M - h.value * PL, c2 = qa % M;
-        static_for<0, 16>([&](auto kk) { v[s.value * 16 + kk.value] = lds[lr * PA + c2 * 17 + kk.value]; });
-      }
-    });
-    if constexpr (NR == 2) {
-      __syncthreads();
-      finish_set(h);
-    }
+  static_for<0, SB>([&](auto s) {
+    const unsigned qb = tid + T * s.value;
+    const unsigned o = (qb / 16) * 17 + qb % 16;
+    static_for<0, M>([&](auto r2) { lds[r2.value * PA + o] = v[s.value * M + r2.value]; });
   });
-  if constexpr (NR == 1) static_for<0, SA>([&](auto s) { finish_set(s); });
+  __syncthreads();
+  static_for<0, SA>([&](auto s) {
+    const unsigned qa = tid + T * s.value;
+    const unsigned r2 = qa / M, c2 = qa % M;
+    static_for<0, 16>([&](auto kk) { v[s.value * 16 + kk.value] = lds[r2 * PA + c2 * 17 + kk.value]; });
+  });
+  static_for<0, SA>([&](auto s) { finish_set(s); });
 
   // ---- per-pattern metric partials (float64 block sums) ----------------------
   double acc[MF_COUNT] = {ef_n, ef_d, ec_n, ec_d, dx_n, dx_d};
@@ -533,21 +467,19 @@ __global__ __launch_bounds__(256) void flush_kernel(FlushParams p) {
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+template <int N, int T, class St, int MODE>
+static void launch_fused_mode(const DivideParams& p, int n_patterns, hipStream_t s) {
+  hipLaunchKernelGGL((divide_fused_kernel<N, T, St, MODE>), dim3(n_patterns), dim3(T), 0, s, p);
+}
+
 template <int N, int T, class St>
 static hipError_t launch_fused(const DivideParams& p, int n_patterns, hipStream_t s) {
   switch (prologue_mode(p)) {
-    case PRO_GENERAL:
-      hipLaunchKernelGGL((divide_fused_kernel<N, T, St, PRO_GENERAL>), dim3(n_patterns), dim3(T), 0, s, p);
-      break;
-    case PRO_MATERIAL:
-      hipLaunchKernelGGL((divide_fused_kernel<N, T, St, PRO_MATERIAL>), dim3(n_patterns), dim3(T), 0, s, p);
-      break;
-    case PRO_INIT:
-      hipLaunchKernelGGL((divide_fused_kernel<N, T, St, PRO_INIT>), dim3(n_patterns), dim3(T), 0, s, p);
-      break;
-    default:
-      hipLaunchKernelGGL((divide_fused_kernel<N, T, St, PRO_FLAGS>), dim3(n_patterns), dim3(T), 0, s, p);
-      break;
+    case PRO_GENERAL: launch_fused_mode<N, T, St, PRO_GENERAL>(p, n_patterns, s); break;
+    case PRO_UPDATE: launch_fused_mode<N, T, St, PRO_UPDATE>(p, n_patterns, s); break;
+    case PRO_MATERIAL: launch_fused_mode<N, T, St, PRO_MATERIAL>(p, n_patterns, s); break;
+    case PRO_INIT: launch_fused_mode<N, T, St, PRO_INIT>(p, n_patterns, s); break;
+    default: launch_fused_mode<N, T, St, PRO_FLAGS>(p, n_patterns, s); break;
   }
   return hipGetLastError();
 }
@@ -622,7 +554,6 @@ __global__ void amp_prepare_kernel(const float* __restrict__ I, float* __restric
                                    int* bad) {
   const size_t nn = size_t(n) * n;
   const size_t total = nn * J;
-  const int M = n / 4;
   for (size_t g = blockIdx.x * size_t(blockDim.x) + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
     const size_t j = g / nn;
     const int rem = int(g % nn);
@@ -631,7 +562,7 @@ __global__ void amp_prepare_kernel(const float* __restrict__ I, float* __restric
       src = g;
     } else {
       const int kc2 = rem / (4 * n), qc = rem % (4 * n);
-      const int kr2 = qc / 16, kk = qc % 16;
+      const int kr2 = qc / 16, kk = qc % 16;  // spectral order of the fused kernel's stage C
       const int kr = kk / 4 + 4 * kr2, kc = kk % 4 + 4 * kc2;
       src = j * nn + size_t(kr) * n + kc;
     }

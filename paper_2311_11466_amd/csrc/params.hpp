@@ -34,6 +34,23 @@ struct DivideParams {
   int nslot;
 };
 
+// Metric finalisation of one iteration: a fixed-order two-level float64
+// reduction of the per-pattern partials into the history ring.  The object
+// launch sums one slice per work-group into part2; after that kernel has
+// finished, one work-group of the finalise launch adds the slice sums in
+// order (a kernel boundary, not a device-wide fence, publishes part2).
+struct MetricParams {
+  const double* met;      // [J][nslot][MF_COUNT]
+  int J, nslot;
+  double* part2;          // [slices][MF_COUNT]
+  int slices;
+  double* ring;           // [cap][kRingFields]
+  int cap;
+  long long k_cur;        // iteration whose Fourier error is in met (-1: none)
+  long long k_prev;       // iteration whose consistency / change are in met (-1: none)
+  int ec_ok, dx_ok;
+};
+
 struct ObjParams {
   const void* y;
   float inv_scale;
@@ -47,8 +64,11 @@ struct ObjParams {
   const float* pmax_part; // [npb] partial maxima of |P|^2
   int npb;
   double tau;
+  MetricParams mp;        // the object launch also finalises the metrics
 };
 
+// Probe partial sums over position chunks (one work-group per 256-pixel
+// block and chunk).
 struct ProbeParams {
   const void* y;
   float inv_scale;
@@ -58,22 +78,18 @@ struct ProbeParams {
   double* part;           // [3][G][N*N]: Re N_P, Im N_P, D_P
 };
 
+// Finalise: probe blocks add the chunks in ascending order, apply the guard
+// and write the probe and its per-block maxima; the metrics block (index
+// npb) finishes the metric reduction.
 struct FinalParams {
-  const double* part;     // as ProbeParams::part
+  const double* part;
   float2* probe;
-  float* pmax_part;
-  const float* tile_max;
+  float* pmax_part;       // [npb]
+  const float* tile_max;  // [n_tiles]
   int n_tiles, N, G, npb;
   double tau;
-  int first_block;        // npb to run the metrics block only
-  // metrics
-  const double* met;
-  int J, nslot;
-  double* ring;           // [cap][kRingFields]
-  int cap;
-  long long k_cur;        // iteration whose Fourier error is in met (-1: none)
-  long long k_prev;       // iteration whose consistency / change are in met (-1: none)
-  int ec_ok, dx_ok;
+  int first_block;        // npb: run the metrics block only
+  MetricParams mp;
 };
 
 struct FlushParams {
@@ -98,9 +114,9 @@ hipError_t launch_divide_stage(int n, int fp16, const DivideParams& p, int n_pat
 int divide_stages(int n);
 hipError_t launch_object_update(int fp16, const ObjParams& p, hipStream_t s);
 hipError_t launch_probe_partial(int fp16, const ProbeParams& p, hipStream_t s);
-hipError_t launch_probe_final(const FinalParams& p, int update_probe, hipStream_t s);
 hipError_t launch_flush(int fp16, const FlushParams& p, int J, hipStream_t s);
-hipError_t launch_metrics_only_final(const FinalParams& p, hipStream_t s);
+hipError_t launch_probe_final(const FinalParams& p, int update_probe, hipStream_t s);
+hipError_t launch_metric_slices(const MetricParams& p, hipStream_t s);
 hipError_t launch_amp_prepare(int n, const float* intensity, float* amp, int J, int* bad, hipStream_t s);
 hipError_t launch_max_abs2_parts(const float2* a, size_t count, float* parts, int nparts, hipStream_t s);
 hipError_t launch_convert_state(int fp16, int to_store, const float2* src, void* dst_store,
