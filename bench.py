@@ -163,11 +163,14 @@ def bench(args):
                 "algorithmic_bytes_per_launch": d["algorithmic_bytes"]}
 
     if args.copy_probe:
-        # a plain copy of known size, for scaling rocprofv3 FETCH/WRITE counters
-        src = torch.empty(args.copy_probe_bytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
+        # a plain elementwise kernel of known traffic (reads 2 B, writes B bytes), for
+        # scaling the rocprofv3 FETCH_SIZE / WRITE_SIZE counters
+        nf = args.copy_probe_bytes // 4
+        a = torch.ones(nf, dtype=torch.float32, device=dev)
+        b = torch.ones(nf, dtype=torch.float32, device=dev)
+        c = torch.empty(nf, dtype=torch.float32, device=dev)
         for _ in range(3):
-            dst.copy_(src)
+            torch.add(a, b, out=c)
         torch.cuda.synchronize()
 
     cpu = None
@@ -260,8 +263,9 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int
     """Turn two rocprofv3 --pmc counter CSVs into the traffic file bench.py reads.
 
     FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by the
-    ratio of known bytes to the same counter's reading on the copy kernel
-    (torch's elementwise copy of copy_bytes bytes).
+    ratio of known bytes to the same counter's reading on the calibration
+    kernel (torch's elementwise add of two copy_bytes arrays into a third:
+    2 * copy_bytes read, copy_bytes written).
     """
     import csv
     import statistics
@@ -283,10 +287,10 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int
     def pick(rows, key):
         vals = [v for k, vs in rows.items() if key in k for v in vs]
         return statistics.median(vals) if vals else None
-    copy_key = "copy"
+    copy_key = "CUDAFunctor_add"
     f_copy = pick(fetch, copy_key)
     w_copy = pick(write, copy_key)
-    f_scale = copy_bytes / (f_copy * 1024) if f_copy else None
+    f_scale = 2 * copy_bytes / (f_copy * 1024) if f_copy else None
     w_scale = copy_bytes / (w_copy * 1024) if w_copy else None
     src_hash = kernel_source_hash()
     for cls, kname in KERNEL_NAMES.items():
@@ -320,7 +324,8 @@ def main():
     ap.add_argument("--param", type=float, default=0.75)
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true", help="also run a plain copy of known size")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run an elementwise add of known traffic (counter calibration)")
     ap.add_argument("--copy-probe-bytes", type=int, default=1 << 30)
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
