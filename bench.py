@@ -65,12 +65,15 @@ def algorithmic_bytes(kind: str, n: int, J: int, abc, blind: bool, storage: str,
     read y once each.  Object/probe gathers and the float64 partial sums are
     not counted (they are cache-resident or small).
     """
+    from paper_2311_11466_amd import uses_blend_form
     a, b, _ = abc
     e = 4 if storage == "fp16" else 8
     rx = e if (abs(1 - a) > 0 or full_metrics) else 0
     ry = e if (abs(a * (1 - b)) > 0 or full_metrics) else 0
     nn = n * n * J
     if kind == "divide":
+        if uses_blend_form(n, a, b, full_metrics):
+            return (e + 4 + e + e) * nn             # w_{k-1}, sqrt(I) in; w_k, y_k out
         if n == 256:
             return (rx + ry + rx + 8) * nn          # rows forward: x, y in; x out; intermediate out
         return (rx + ry + 4 + rx + e) * nn
@@ -123,12 +126,13 @@ def bench(args):
     scan = make_workload(args.workload)
     abc = pk.preset(args.algorithm, args.param)
     cfg = scan.config
+    full_metrics = args.metrics == "all"
     print(f"# workload {cfg.name}: object {cfg.obj_h}x{cfg.obj_w}, N={cfg.n}, J={scan.n_pos}", file=sys.stderr,
           flush=True)
     g = pk.Scan(torch.as_tensor(scan.pos).to(dev), torch.as_tensor(scan.intensity).to(dev),
                 torch.as_tensor(scan.obj0.astype(np.complex64)).to(dev),
                 torch.as_tensor(scan.probe0.astype(np.complex64)).to(dev),
-                storage=args.storage, blind=True, device=dev)
+                storage=args.storage, blind=True, device=dev, full_metrics=full_metrics)
     g.set_algorithm(*abc)
     g.iterate(args.warmup)
     torch.cuda.synchronize()
@@ -149,7 +153,7 @@ def bench(args):
         if cnt == 0:
             continue
         avg_us = ms / cnt * 1e3
-        nbytes = algorithmic_bytes(k, cfg.n, scan.n_pos, abc, True, args.storage)
+        nbytes = algorithmic_bytes(k, cfg.n, scan.n_pos, abc, True, args.storage, full_metrics)
         kernels[k] = {"avg_us": round(avg_us, 3), "launches": cnt,
                       "share": round(ms / (dt * 1e3), 4),
                       "algorithmic_bytes": nbytes,
@@ -198,6 +202,10 @@ def bench(args):
                    "algorithm": f"{args.algorithm}({args.param})" if args.algorithm in ("RAAR", "RRR", "TLAMBDA")
                    else args.algorithm,
                    "abc": list(abc), "blind": True, "storage": args.storage, "accumulate": "fp64",
+                   "metrics": ("fourier, consistency and change errors every iteration" if full_metrics
+                               else "fourier error every iteration"),
+                   "exit_wave_state": "w = (1-a) x + a(1-b) y" if pk.uses_blend_form(cfg.n, abc[0], abc[1],
+                                                                                     full_metrics) else "x",
                    "photons": cfg.photons, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -316,6 +324,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="scan_n128",
                     choices=["scan_n128", "large_n256", "tiny_n32", "served"])
+    ap.add_argument("--metrics", default="all", choices=["all", "fourier"],
+                    help="all: Fourier, consistency and change errors every iteration; "
+                         "fourier: the Fourier error only (enables the blend form)")
     ap.add_argument("--requests", type=int, default=32, help="served: number of requests")
     ap.add_argument("--rate-factor", type=float, default=0.7, help="served: arrival rate / closed-loop capacity")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served: HBM budget")

@@ -95,8 +95,14 @@ typedef struct {
   int32_t probe_update_start; /* blind: probe updated from this iteration on     */
   int32_t full_metrics;       /* 1: compute all three metrics every iteration
                                  (forces x and y to be kept even where (a,b,c)
-                                 would not need them); 0: only those whose
-                                 inputs are read anyway (others are NaN)       */
+                                 would not need them); 0: the Fourier error
+                                 every iteration, the other two only where
+                                 their inputs are read anyway (else NaN).
+                                 With 0, N <= 128 and a != 1, b != 1 the
+                                 library keeps w = (1-a) x + a(1-b) y in place
+                                 of x between iterations (one read fewer per
+                                 pixel); consistency and change are then NaN.
+                                 pty_get_state still returns x.               */
   int32_t metric_capacity;    /* entries of the metric history ring; 0: 4096    */
   double tau;                 /* division guard; 0 selects 1e-10                 */
 } pty_scan_desc;

@@ -308,22 +308,35 @@ def workspace_bytes(n: int, n_pos: int, obj_h: int, obj_w: int, storage: str = "
     return int(L.pty_workspace_bytes(ctypes.byref(d)))
 
 
+def uses_blend_form(n: int, a: float, b: float, full_metrics: bool) -> bool:
+    """Whether the library keeps w = (1-a) x + a(1-b) y in place of x between
+    iterations (the same rule as the library: no full metrics, N <= 128, and
+    both coefficients non-zero in float32)."""
+    import numpy as np
+    return (not full_metrics and n <= 128 and np.float32(1.0 - a) != 0
+            and np.float32(a * (1.0 - b)) != 0)
+
+
 def algorithmic_bytes_per_projection(n: int, a: float, b: float, blind: bool = True,
                                      storage: str = "fp32", full_metrics: bool = True) -> int:
     """HBM bytes one diffraction pattern moves in one iteration (the roofline model).
 
     divide: read x_{k-1} (if 1-a != 0 or metrics), y_{k-1} (if a(1-b) != 0 or
-    metrics), sqrt(I) (4 B); write x_k (same condition as its read), y_k.
+    metrics), sqrt(I) (4 B); write x_k (same condition as its read), y_k.  In
+    the blend form: read w_{k-1} and sqrt(I), write w_k and y_k.
     concur: read y_k once for the object, once more for the probe (blind).
     """
     e = 4 if storage == "fp16" else 8
     nn = n * n
-    rx = e if (abs(1 - a) > 0 or full_metrics) else 0
-    ry = e if (abs(a * (1 - b)) > 0 or full_metrics) else 0
-    divide = rx + ry + 4 + rx + e
+    if uses_blend_form(n, a, b, full_metrics):
+        divide = e + 4 + e + e
+    else:
+        rx = e if (abs(1 - a) > 0 or full_metrics) else 0
+        ry = e if (abs(a * (1 - b)) > 0 or full_metrics) else 0
+        divide = rx + ry + 4 + rx + e
     concur = e + (e if blind else 0)
     return (divide + concur) * nn
 
 
 __all__ = ["Scan", "iterate_many", "load_library", "preset", "workspace_bytes", "PtyError",
-           "algorithmic_bytes_per_projection", "EXPORTS", "LIB_PATH"]
+           "algorithmic_bytes_per_projection", "uses_blend_form", "EXPORTS", "LIB_PATH"]

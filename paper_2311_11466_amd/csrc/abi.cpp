@@ -34,7 +34,13 @@ constexpr double kDefaultTau = 1e-10;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // exit-wave state of the next divide prologue
-enum Mode { MODE_INIT = 0, MODE_MATERIAL = 1, MODE_PENDING = 2 };
+// State of the exit-wave buffers between iterations:
+//   MODE_INIT       nothing stored; x_0 = P S_j O
+//   MODE_MATERIAL   x holds x_k
+//   MODE_PENDING    x, y hold x_{k-1}, y_{k-1}; x_k = pa P S_j O + pb y + pg x
+//   MODE_PENDING_W  x holds the blend w_{k-1} = pg x_{k-1} + pb y_{k-1},
+//                   y holds y_{k-1}; x_k = pa P S_j O + w
+enum Mode { MODE_INIT = 0, MODE_MATERIAL = 1, MODE_PENDING = 2, MODE_PENDING_W = 3 };
 
 struct Layout {
   size_t amp, x, y, tmp, obj, probe, pos, tile_off, tile_list, part, met, met2, ring, tile_max, pmax, tw, flag,
@@ -222,8 +228,24 @@ FinalParams final_params(const pty_scan* s, const MetricParams& mp) {
 }
 
 // One iteration: divide (with the pending update), object (+ metrics), [probe].
+pty_status flush(pty_scan* s, bool materialise);
+
+// Blend form (x buffer holds w, see MODE_PENDING_W): it saves the y read of
+// the next prologue when x and y are both needed, i.e. a != 1 and b != 1.
+// It leaves no x_k for the change metric, so it is used only without
+// full_metrics, and only by the fused divide (N <= 128).
+bool use_blend(const pty_scan* s) {
+  return !s->full_metrics && s->N <= 128 && float(1.0 - s->a) != 0.f && float(s->a * (1.0 - s->b)) != 0.f;
+}
+
 pty_status launch_iteration(pty_scan* s) {
   const hipStream_t st = s->stream;
+  const bool wf = use_blend(s);
+  if ((wf && s->mode == MODE_PENDING) || (!wf && s->mode == MODE_PENDING_W)) {
+    // a change of form passes through a materialised x
+    const pty_status fs = flush(s, true);
+    if (fs != PTY_OK) return fs;
+  }
   DivideParams p{};
   p.obj = s->at<float2>(s->L.obj);
   p.probe = s->at<float2>(s->L.probe);
@@ -247,7 +269,18 @@ pty_status launch_iteration(pty_scan* s) {
   p.prev_dx = want_prev && s->x_valid && (need_x || s->full_metrics);
   p.read_y = need_y || p.prev_ec;
   p.read_x = need_x || p.prev_dx;
-  const bool write_x = (1.0 - s->a) != 0.0 || s->full_metrics;
+  bool write_x = (1.0 - s->a) != 0.0 || s->full_metrics;
+  if (wf) {
+    p.wform = 1;
+    if (s->mode == MODE_INIT) { p.alpha = 1.f; p.read_x = 0; }
+    else if (s->mode == MODE_MATERIAL) { p.alpha = 0.f; p.read_x = 1; }
+    else { p.alpha = s->pa; p.read_x = s->x_valid; }
+    p.beta = 0.f; p.gamma = 0.f;
+    p.read_y = 0; p.prev_ec = 0; p.prev_dx = 0;
+    p.next_beta = float(s->a * (1.0 - s->b));
+    p.next_gamma = float(1.0 - s->a);
+    write_x = true;
+  }
   p.write_x = write_x;
   p.c = float(s->c);
   p.scale = s->scale;
@@ -300,13 +333,13 @@ pty_status launch_iteration(pty_scan* s) {
   PTY_HIP(s, timed(s, PTY_K_FINAL, [&] { return launch_probe_final(f, update_probe, st); }), "finalise launch");
 
   // the new state is pending with this iteration's (a, b)
-  s->mode = MODE_PENDING;
+  s->mode = wf ? MODE_PENDING_W : MODE_PENDING;
   s->pa = float(s->a * s->b);
   s->pb = float(s->a * (1.0 - s->b));
   s->pg = float(1.0 - s->a);
   s->x_valid = write_x;
   s->y_valid = true;
-  s->prev_metrics_done = false;
+  s->prev_metrics_done = wf;   // the blend form has no consistency / change metrics
   s->k += 1;
   return PTY_OK;
 }
@@ -329,6 +362,12 @@ pty_status flush(pty_scan* s, bool materialise) {
   else { fp.alpha = s->pa; fp.beta = s->pb; fp.gamma = s->pg; }
   fp.read_x = (s->x_valid && (fp.gamma != 0.f || want_metrics)) ? 1 : 0;
   fp.read_y = (s->y_valid && (fp.beta != 0.f || want_metrics)) ? 1 : 0;
+  if (s->mode == MODE_PENDING_W) {
+    fp.wform = 1;
+    fp.beta = 0.f; fp.gamma = 0.f;
+    fp.read_x = s->x_valid ? 1 : 0;
+    fp.read_y = 0;
+  }
   fp.scale = s->scale;
   fp.inv_scale = s->inv_scale;
   fp.write_x = materialise && s->mode != MODE_MATERIAL;

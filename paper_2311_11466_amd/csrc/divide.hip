@@ -38,6 +38,16 @@ __device__ __forceinline__ float2 update_x(float2 z, float2 yo, float2 xo, float
   return r;
 }
 
+// Blend form: x_k = alpha z + w, one fused multiply-add per component.
+__device__ __forceinline__ float2 blend_x(float2 z, float2 w, float al) {
+  return make_float2(fmaf(al, z.x, w.x), fmaf(al, z.y, w.y));
+}
+
+// Blend form: w_k = gamma x_k + beta y_k.
+__device__ __forceinline__ float2 blend_w(float2 x, float2 y, float be, float ga) {
+  return make_float2(fmaf(ga, x.x, be * y.x), fmaf(ga, x.y, be * y.y));
+}
+
 // Relaxed modulus projection of one spectrum value, already scaled by 1/N^2
 // for the inverse transform: X (c A / |X| + 1 - c) / N^2, and c A / N^2 (phase
 // 0) where X = 0.  |X|^2 below the smallest normal float counts as zero.
@@ -61,21 +71,32 @@ __device__ __forceinline__ float2 fourier_op(float2 X, float A, float c, float o
 }
 
 // Which exit-wave buffers the divide prologue touches.  The common cases are
-// compile-time so no load sits behind a per-element branch.
-enum ProMode { PRO_GENERAL = 0, PRO_UPDATE = 1, PRO_MATERIAL = 2, PRO_INIT = 3, PRO_FLAGS = 4 };
+// compile-time so no load sits behind a per-element branch.  The PRO_W_*
+// modes are the blend form: PRO_W_PENDING reads w and gathers P S_j O,
+// PRO_W_MATERIAL reads a materialised x (alpha = 0), PRO_W_ZERO gathers only
+// (w = 0: the first iteration, or a blend with beta' = gamma' = 0).
+enum ProMode {
+  PRO_GENERAL = 0, PRO_UPDATE = 1, PRO_MATERIAL = 2, PRO_INIT = 3, PRO_FLAGS = 4,
+  PRO_W_PENDING = 5, PRO_W_MATERIAL = 6, PRO_W_ZERO = 7
+};
 
 template <int MODE>
 struct Pro {
-  static constexpr bool rx(const DivideParams& p) { return MODE == PRO_FLAGS ? p.read_x : MODE != PRO_INIT; }
+  static constexpr bool wf = MODE >= PRO_W_PENDING;
+  static constexpr bool gather = MODE != PRO_W_MATERIAL;
+  static constexpr bool rx(const DivideParams& p) {
+    return MODE == PRO_FLAGS ? p.read_x : (MODE != PRO_INIT && MODE != PRO_W_ZERO);
+  }
   static constexpr bool ry(const DivideParams& p) {
     return MODE == PRO_FLAGS ? p.read_y : (MODE == PRO_GENERAL || MODE == PRO_UPDATE);
   }
-  static constexpr bool wx(const DivideParams& p) { return MODE == PRO_FLAGS ? p.write_x : true; }
+  static constexpr bool wx(const DivideParams& p) { return MODE == PRO_FLAGS ? p.write_x : !wf; }
   static constexpr bool ec(const DivideParams& p) { return MODE == PRO_FLAGS ? p.prev_ec : MODE == PRO_GENERAL; }
   static constexpr bool dx(const DivideParams& p) { return MODE == PRO_FLAGS ? p.prev_dx : MODE == PRO_GENERAL; }
 };
 
 int prologue_mode(const DivideParams& p) {
+  if (p.wform) return p.read_x ? (p.alpha != 0.f ? PRO_W_PENDING : PRO_W_MATERIAL) : PRO_W_ZERO;
   const bool met = p.prev_ec || p.prev_dx;
   if (p.read_x && p.read_y && p.write_x && p.prev_ec && p.prev_dx) return PRO_GENERAL;
   if (p.read_x && p.read_y && p.write_x && !met) return PRO_UPDATE;
@@ -128,8 +149,10 @@ void divide_fused_kernel(DivideParams p) {
   const float2* __restrict__ tw = p.tw;
   const unsigned ow = p.obj_w;
   const bool rx = PR::rx(p), ry = PR::ry(p), wx = PR::wx(p), mec = PR::ec(p), mdx = PR::dx(p);
+  const bool wx_blend = PR::wf && p.write_x;   // wave-uniform
 
   float2 v[E];
+  float2 xk[PR::wf ? E : 1];   // blend form: x_k, kept for w_k (registers are not the limit: LDS is)
   float ec_n = 0.f, ec_d = 0.f, dx_n = 0.f, dx_d = 0.f, ef_n = 0.f, ef_d = 0.f;
 
   // ---- prologue and stage A, set by set -----------------------------------
@@ -146,8 +169,8 @@ void divide_fused_kernel(DivideParams p) {
         constexpr int r1 = e / 4, c1 = e % 4;
         const unsigned r = r2 + M * r1, c = c2 + M * c1;
         const unsigned idx = r * N + c;
-        zp[q.value] = pb[idx];
-        zo[q.value] = ob[r * ow + c];
+        zp[q.value] = PR::gather ? pb[idx] : make_float2(0.f, 0.f);
+        zo[q.value] = PR::gather ? ob[r * ow + c] : make_float2(0.f, 0.f);
         xo[q.value] = rx ? St::load(xb, idx, p.inv_scale) : make_float2(0.f, 0.f);
         yo[q.value] = ry ? St::load(yb, idx, p.inv_scale) : make_float2(0.f, 0.f);
       });
@@ -155,8 +178,9 @@ void divide_fused_kernel(DivideParams p) {
         constexpr int e = g0.value + q.value;
         constexpr int r1 = e / 4, c1 = e % 4;
         const unsigned idx = (r2 + M * r1) * N + (c2 + M * c1);
-        const float2 z = cmul(zp[q.value], zo[q.value]);
-        const float2 xn = update_x(z, yo[q.value], xo[q.value], p.alpha, p.beta, p.gamma);
+        const float2 z = PR::gather ? cmul(zp[q.value], zo[q.value]) : make_float2(0.f, 0.f);
+        const float2 xn = PR::wf ? blend_x(z, xo[q.value], p.alpha)
+                                 : update_x(z, yo[q.value], xo[q.value], p.alpha, p.beta, p.gamma);
         if (mec) {
           const float dr = z.x - yo[q.value].x, di = z.y - yo[q.value].y;
           ec_n = fmaf(dr, dr, fmaf(di, di, ec_n));
@@ -168,6 +192,7 @@ void divide_fused_kernel(DivideParams p) {
           dx_d = fmaf(xo[q.value].x, xo[q.value].x, fmaf(xo[q.value].y, xo[q.value].y, dx_d));
         }
         if (wx) St::store(xb, idx, xn, p.scale);
+        if constexpr (PR::wf) xk[s.value * 16 + e] = xn;
         v[s.value * 16 + e] = xn;
       });
       __builtin_amdgcn_sched_barrier(0);
@@ -273,10 +298,22 @@ void divide_fused_kernel(DivideParams p) {
       v[s.value * 16 + e.value] = t;
     });
     dft4x4_reg<true, s.value * 16>(v);
-    static_for<0, 16>([&](auto e) {
-      constexpr int r1 = e.value / 4, c1 = e.value % 4;
-      St::store(yb, (r2 + M * r1) * N + (c2 + M * c1), v[s.value * 16 + e.value], p.scale);
-    });
+    if (PR::wf && wx_blend) {
+      // blend form: w_k from the x_k kept in registers since the prologue
+      static_for<0, 16>([&](auto e) {
+        constexpr int r1 = e.value / 4, c1 = e.value % 4;
+        const unsigned idx = (r2 + M * r1) * N + (c2 + M * c1);
+        const float2 yk = v[s.value * 16 + e.value];
+        St::store(yb, idx, yk, p.scale);
+        St::store(xb, idx, blend_w(xk[PR::wf ? s.value * 16 + e.value : 0], yk, p.next_beta, p.next_gamma),
+                  p.scale);
+      });
+    } else {
+      static_for<0, 16>([&](auto e) {
+        constexpr int r1 = e.value / 4, c1 = e.value % 4;
+        St::store(yb, (r2 + M * r1) * N + (c2 + M * c1), v[s.value * 16 + e.value], p.scale);
+      });
+    }
     __builtin_amdgcn_sched_barrier(0);
   };
   static_for<0, SB>([&](auto s) {
@@ -445,7 +482,7 @@ __global__ __launch_bounds__(256) void flush_kernel(FlushParams p) {
     float2 xo = make_float2(0.f, 0.f), yo = make_float2(0.f, 0.f);
     if (p.read_x) xo = St::load(xs, base + idx, p.inv_scale);
     if (p.read_y) yo = St::load(ys, base + idx, p.inv_scale);
-    const float2 xn = update_x(z, yo, xo, p.alpha, p.beta, p.gamma);
+    const float2 xn = p.wform ? blend_x(z, xo, p.alpha) : update_x(z, yo, xo, p.alpha, p.beta, p.gamma);
     double dr = double(z.x) - double(yo.x), di = double(z.y) - double(yo.y);
     acc[0] += dr * dr + di * di;
     acc[1] += double(yo.x) * yo.x + double(yo.y) * yo.y;
@@ -479,6 +516,9 @@ static hipError_t launch_fused(const DivideParams& p, int n_patterns, hipStream_
     case PRO_UPDATE: launch_fused_mode<N, T, St, PRO_UPDATE>(p, n_patterns, s); break;
     case PRO_MATERIAL: launch_fused_mode<N, T, St, PRO_MATERIAL>(p, n_patterns, s); break;
     case PRO_INIT: launch_fused_mode<N, T, St, PRO_INIT>(p, n_patterns, s); break;
+    case PRO_W_PENDING: launch_fused_mode<N, T, St, PRO_W_PENDING>(p, n_patterns, s); break;
+    case PRO_W_MATERIAL: launch_fused_mode<N, T, St, PRO_W_MATERIAL>(p, n_patterns, s); break;
+    case PRO_W_ZERO: launch_fused_mode<N, T, St, PRO_W_ZERO>(p, n_patterns, s); break;
     default: launch_fused_mode<N, T, St, PRO_FLAGS>(p, n_patterns, s); break;
   }
   return hipGetLastError();
@@ -526,6 +566,7 @@ static hipError_t launch_stage_t(int n, const DivideParams& p, int n_patterns, i
     if (stage != 0) return hipErrorInvalidValue;
     return launch_divide_t<St>(n, p, n_patterns, s);
   }
+  if (p.wform) return hipErrorInvalidValue;   // the three-pass form keeps x
   const dim3 grid(16, n_patterns);
   switch (stage) {
     case 0: hipLaunchKernelGGL((rows256_fwd_kernel<St>), grid, dim3(256), 0, s, p); break;

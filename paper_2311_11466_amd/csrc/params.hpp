@@ -32,6 +32,13 @@ struct DivideParams {
   int prev_ec, prev_dx;   // accumulate consistency / change partials of the previous iteration
   double* met;            // [J][nslot][MF_COUNT]
   int nslot;
+  // Blend form (fused kernel only).  The x buffer holds the blend
+  //   w_{k-1} = gamma' x_{k-1} + beta' y_{k-1}
+  // of the previous iteration, the prologue forms x_k = alpha * P S_j O + w_{k-1}
+  // (read_x = 0: w is zero), and the epilogue forms x_k again the same way and
+  // stores w_k = next_gamma * x_k + next_beta * y_k (if write_x) beside y_k.
+  int wform;
+  float next_beta, next_gamma;
 };
 
 // Metric finalisation of one iteration: a fixed-order two-level float64
@@ -105,6 +112,7 @@ struct FlushParams {
   int write_x;
   double* met;
   int nslot;
+  int wform;              // x holds the blend w: x = alpha * P S_j O + w, no metrics
 };
 
 // ---- launchers (return hipGetLastError() of the launch) ----

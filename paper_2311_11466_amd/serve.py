@@ -127,7 +127,8 @@ class Server:
             scan = Scan(torch.as_tensor(req.pos).to(dev, non_blocking=False),
                         torch.as_tensor(req.intensity).to(dev),
                         torch.as_tensor(req.obj0).to(dev), torch.as_tensor(req.probe0).to(dev),
-                        storage=req.storage, blind=True, device=dev, stream=stream)
+                        storage=req.storage, blind=True, device=dev, stream=stream,
+                        full_metrics=False)   # completion reads the Fourier error only
         scan.set_algorithm(*req.abc)
         return _Active(req, scan, stream, now, scan.workspace_bytes)
 
