@@ -38,10 +38,19 @@ KERNEL_NAMES = {
     "divide": "divide_fused_kernel",
     "divide_cols": "cols256_kernel",
     "divide_rows_inv": "rows256_inv_kernel",
-    "object": "object_update_kernel",
+    "object": "object_lds_kernel",
     "probe": "probe_partial_kernel",
     "final": "probe_final_kernel",
 }
+
+
+def kernel_name(cls: str, n: int) -> str:
+    """The HIP kernel behind a kernel class at pattern size n."""
+    if n == 256 and cls == "divide":
+        return "rows256_fwd_kernel"
+    if n == 256 and cls == "object":
+        return "object_update_kernel"
+    return KERNEL_NAMES[cls]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{workload}.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_11466_amd", "csrc", f)
                   for f in ("divide.hip", "concur.hip", "common.hpp", "params.hpp")]
@@ -163,7 +172,7 @@ def bench(args):
     traffic = load_traffic(dom, cfg.name)
     roofline = {"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(d["GBs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": KERNEL_NAMES[dom], "avg_us": d["avg_us"],
+                "kernel": kernel_name(dom, cfg.n), "avg_us": d["avg_us"],
                 "algorithmic_bytes_per_launch": d["algorithmic_bytes"]}
 
     if args.copy_probe:
@@ -301,7 +310,10 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int
     f_scale = 2 * copy_bytes / (f_copy * 1024) if f_copy else None
     w_scale = copy_bytes / (w_copy * 1024) if w_copy else None
     src_hash = kernel_source_hash()
-    for cls, kname in KERNEL_NAMES.items():
+    from ptysynth.scans import CONFIGS
+    n = CONFIGS[workload].n
+    for cls in KERNEL_NAMES:
+        kname = kernel_name(cls, n)
         f = pick(fetch, kname)
         w = pick(write, kname)
         if f is None or w is None or f_scale is None or w_scale is None:

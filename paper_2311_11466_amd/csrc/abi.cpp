@@ -218,7 +218,7 @@ FinalParams final_params(const pty_scan* s, const MetricParams& mp) {
   f.probe = s->at<float2>(s->L.probe);
   f.pmax_part = s->at<float>(s->L.pmax);
   f.tile_max = s->at<float>(s->L.tile_max);
-  f.n_tiles = s->L.n_tiles;
+  f.n_tiles = object_blocks(s->N, s->L.n_tiles);   // tile_max entries the object launch wrote
   f.N = s->N;
   f.G = s->L.G;
   f.npb = s->L.npb;
@@ -309,7 +309,7 @@ pty_status launch_iteration(pty_scan* s) {
   o.pmax_part = s->at<float>(s->L.pmax);
   o.npb = s->L.npb;
   o.tau = s->tau;
-  o.mp = metric_params(s, s->L.n_tiles);
+  o.mp = metric_params(s, object_blocks(s->N, s->L.n_tiles));
   o.mp.k_cur = s->k;
   o.mp.k_prev = (p.prev_ec || p.prev_dx) ? s->k - 1 : -1;
   o.mp.ec_ok = p.prev_ec;

@@ -194,7 +194,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
     for (int q = 0; q < NV; ++q) red[q * NW + wave] = v[q];
   }
   __syncthreads();
-#pragma unroll
+  // one value at a time for many waves (NV * NW loads in flight would spill)
+#pragma unroll(NW > 4 ? 1 : NV)
   for (int q = 0; q < NV; ++q) {
     double s = 0.0;
 #pragma unroll
@@ -202,6 +203,20 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
     v[q] = s;
   }
   __syncthreads();
+}
+
+// Work-groups of one launch go to the 8 XCDs (each with its own L2) in
+// round-robin order of their id.  xcd_block maps the id so that every XCD
+// runs a contiguous range of logical blocks: neighbouring blocks, which read
+// overlapping object pixels, then share an L2.  The grid is padded to a
+// multiple of 8 (xcd_pad); logical ids beyond the real count exit at once.
+constexpr int kXcds = 8;
+__host__ __device__ constexpr int xcd_pad(int n) { return (n + kXcds - 1) / kXcds * kXcds; }
+#ifndef PTY_XCD_MAP
+#define PTY_XCD_MAP 1
+#endif
+__device__ __forceinline__ int xcd_block(int b, int padded) {
+  return PTY_XCD_MAP ? (b % kXcds) * (padded / kXcds) + b / kXcds : b;
 }
 
 template <int NT>

@@ -4,14 +4,17 @@
 //   probe   P(u) = sum_j conj(S_j O)(u) y_j(u) / sum_j |S_j O(u)|^2    (blind)
 //
 // Object: the object is cut into 64 x 16 tiles; each tile has the ascending
-// list of scan positions whose window meets it (built on the host).  One
-// work-group owns one tile, one thread a column of four pixels, and sums over
-// its list in list order: every exit-wave pixel is read exactly once, no
-// atomics, and the result does not depend on launch order.
-// Probe: a grid of (256-pixel block) x (position chunk) writes float64
-// partial sums; a finalise kernel adds the chunks in ascending order.  The
-// object launch also sums slices of the metric partials, which the finalise
-// kernel's last block adds up.
+// list of scan positions whose window meets it (built on the host).  256
+// threads own one tile, one thread a column of four pixels, and sum over the
+// list in list order: every exit-wave pixel is read exactly once, no atomics,
+// and the result does not depend on launch order.  For N <= 128 a work-group
+// of 1024 threads owns four neighbouring tiles and keeps the probe in LDS.
+// Probe: (position chunk) x (256-pixel block) work-groups write float64
+// partial sums; a finalise kernel adds the chunks in ascending order.  Both
+// launches place neighbouring work on one XCD (xcd_block), so the object
+// pixels a chunk or tile row gathers stay in one L2.  The object launch also
+// sums slices of the metric partials, which the finalise kernel's last block
+// adds up.
 #include "common.hpp"
 #include "params.hpp"
 
@@ -20,7 +23,9 @@ namespace pty {
 constexpr int kTileW = 64;
 constexpr int kTileH = 16;
 
-// Slice `b` of the metric partials, summed in a fixed order into part2[b].
+// Slice `b` of the metric partials, summed in a fixed order into part2[b]
+// by a work-group of NT threads.
+template <int NT = 256>
 __device__ void metric_slice(const MetricParams& p, int b, double* red) {
   double acc[MF_COUNT];
 #pragma unroll
@@ -28,11 +33,11 @@ __device__ void metric_slice(const MetricParams& p, int b, double* red) {
   const int total = p.J * p.nslot;
   const int per = (total + p.slices - 1) / p.slices;
   const int i0 = b * per, i1 = min(total, i0 + per);
-  for (int i = i0 + int(threadIdx.x); i < i1; i += 256) {
+  for (int i = i0 + int(threadIdx.x); i < i1; i += NT) {
 #pragma unroll
     for (int q = 0; q < MF_COUNT; ++q) acc[q] += p.met[size_t(i) * MF_COUNT + q];
   }
-  block_sum<MF_COUNT, 256>(acc, red);
+  block_sum<MF_COUNT, NT>(acc, red);
   if (threadIdx.x < MF_COUNT) p.part2[size_t(b) * MF_COUNT + threadIdx.x] = acc[threadIdx.x];
 }
 
@@ -65,7 +70,7 @@ __device__ void metric_finish(const MetricParams& p, double* red) {
 
 __global__ __launch_bounds__(256) void metric_slice_kernel(MetricParams p) {
   __shared__ double red[MF_COUNT * 4];
-  metric_slice(p, blockIdx.x, red);
+  metric_slice<256>(p, blockIdx.x, red);
 }
 
 // One work-group per 64 x 16 object tile; a thread owns one column and four
@@ -159,7 +164,115 @@ __global__ __launch_bounds__(256) void object_update_kernel(ObjParams p) {
   m = block_max<256>(m, red);
   if (threadIdx.x == 0) p.tile_max[tile] = m;
   __shared__ double mred[MF_COUNT * 4];
-  metric_slice(p.mp, tile, mred);
+  metric_slice<256>(p.mp, tile, mred);
+}
+
+// N <= 128: the probe (at most 128 KiB) is staged in LDS once per work-group
+// and the work-group of 1024 threads owns kGroupTiles tiles, one per 256
+// threads, with the same per-thread arithmetic and order as above; the
+// probe gathers then cost LDS reads instead of cache traffic.  Tile maxima
+// and metric slices are per work-group.
+constexpr int kGroupTiles = 4;
+#ifndef PTY_LDS_UNROLL
+#define PTY_LDS_UNROLL 2
+#endif
+constexpr int kLdsUnroll = PTY_LDS_UNROLL;   // 1024 threads: at most 128 VGPRs each
+
+template <class St, int N>
+__global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
+  __shared__ float2 pl[N * N];
+  __shared__ int4 ent[kGroupTiles][kListChunk];
+  __shared__ float red[16];
+  __shared__ int cnt[kGroupTiles];
+  __shared__ double mred[MF_COUNT * 16];
+  const int blk = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
+  if (blk >= (p.n_tiles + kGroupTiles - 1) / kGroupTiles) return;
+  const int g = threadIdx.x >> 8, lt = threadIdx.x & 255;
+  const int tile = blk * kGroupTiles + g;
+  const bool tile_ok = tile < p.n_tiles;
+  const int tc = tile_ok ? tile : p.n_tiles - 1;
+  const int tx = tc % p.tiles_x, ty = tc / p.tiles_x;
+  const int lane = lt & 63, wave = lt >> 6;
+  const int col = tx * kTileW + lane;
+  const int row0 = ty * kTileH + wave;
+  constexpr size_t NN = size_t(N) * N;
+  using elem = typename St::elem;
+  const elem* ys = reinterpret_cast<const elem*>(p.y);
+
+  for (int i = threadIdx.x; i < N * N; i += 1024) pl[i] = p.probe[i];
+  float pm = 0.0f;
+  for (int i = threadIdx.x; i < p.npb; i += 1024) pm = fmaxf(pm, p.pmax_part[i]);
+  pm = block_max<1024>(pm, red);      // its barriers also publish pl
+  const double thr = p.tau * double(pm);
+
+  const int e0 = tile_ok ? p.tile_off[tile] : 0;
+  const int len = tile_ok ? p.tile_off[tile + 1] - e0 : 0;
+  if (lt == 0) cnt[g] = len;
+  __syncthreads();
+  int maxlen = cnt[0];
+#pragma unroll
+  for (int q = 1; q < kGroupTiles; ++q) maxlen = max(maxlen, cnt[q]);
+
+  double nr[4] = {0, 0, 0, 0}, ni[4] = {0, 0, 0, 0}, dd[4] = {0, 0, 0, 0};
+  for (int c0 = 0; c0 < maxlen; c0 += kListChunk) {   // same trip count in every group
+    const int cn = min(kListChunk, len - c0);
+    __syncthreads();
+    for (int i = lt; i < cn; i += 256) {
+      const int j = p.tile_list[e0 + c0 + i];
+      const int2 pj = p.pos[j];
+      ent[g][i] = make_int4(j, pj.x, pj.y, 0);
+    }
+    __syncthreads();
+    for (int e = 0; e < cn; e += kLdsUnroll) {
+      float2 pv[kLdsUnroll][4], yv[kLdsUnroll][4];
+#pragma unroll
+      for (int q = 0; q < kLdsUnroll; ++q) {
+        const int4 en = ent[g][min(e + q, cn - 1)];
+        const bool live = e + q < cn;
+        const int u1 = col - en.z;
+        const bool cin = live && (unsigned)u1 < (unsigned)N;
+        const int u1c = min(max(u1, 0), N - 1);
+        const elem* yj = ys + size_t(en.x) * NN;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int u0 = row0 + 4 * i - en.y;
+          const bool ok = cin && (unsigned)u0 < (unsigned)N;
+          const int u = min(max(u0, 0), N - 1) * N + u1c;
+          const float2 a = pl[u];
+          const float2 b = St::load(yj, u, p.inv_scale);
+          pv[q][i] = make_float2(ok ? a.x : 0.f, ok ? a.y : 0.f);
+          yv[q][i] = make_float2(ok ? b.x : 0.f, ok ? b.y : 0.f);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kLdsUnroll; ++q) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double px = pv[q][i].x, py = pv[q][i].y, yx = yv[q][i].x, yy = yv[q][i].y;
+          nr[i] += px * yx + py * yy;
+          ni[i] += px * yy - py * yx;
+          dd[i] += px * px + py * py;
+        }
+      }
+    }
+  }
+  float m = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = row0 + 4 * i;
+    if (tile_ok && row < p.H && col < p.W) {
+      const size_t idx = size_t(row) * p.W + col;
+      float2 o = p.obj[idx];
+      if (dd[i] > thr) {
+        o = make_float2(float(nr[i] / dd[i]), float(ni[i] / dd[i]));
+        p.obj[idx] = o;
+      }
+      m = fmaxf(m, cnorm(o));
+    }
+  }
+  m = block_max<1024>(m, red);
+  if (threadIdx.x == 0) p.tile_max[blk] = m;
+  metric_slice<1024>(p.mp, blk, mred);
 }
 
 constexpr int kProbeUnroll = 8;
@@ -168,8 +281,13 @@ template <class St>
 __global__ __launch_bounds__(256) void probe_partial_kernel(ProbeParams p) {
   const int N = p.N;
   const int NN = N * N;
-  const int u = blockIdx.x * 256 + threadIdx.x;
-  const int g = blockIdx.y;
+  // logical block = chunk-major (g, pixel block); each XCD runs whole chunks,
+  // whose object gathers then stay in its L2
+  const int npb = (NN + 255) / 256;
+  const int l = xcd_block(blockIdx.x, gridDim.x);
+  if (l >= npb * p.G) return;
+  const int g = l / npb;
+  const int u = (l % npb) * 256 + threadIdx.x;
   const int j0 = g * p.chunk;
   const int j1 = min(p.J, j0 + p.chunk);
   const int uu = min(u, NN - 1);
@@ -279,14 +397,30 @@ __global__ void convert_kernel(int to_store, const float2* src, typename St::ele
 }
 
 // ---------------------------------------------------------------------------
+int object_blocks(int n, int n_tiles) {
+  return n <= 128 ? (n_tiles + kGroupTiles - 1) / kGroupTiles : n_tiles;
+}
+
+template <class St>
+static void launch_object_t(const ObjParams& p, hipStream_t s) {
+  const dim3 grid(object_blocks(p.N, p.n_tiles));
+  const dim3 gridx(xcd_pad(object_blocks(p.N, p.n_tiles)));
+  switch (p.N) {
+    case 32: hipLaunchKernelGGL((object_lds_kernel<St, 32>), gridx, dim3(1024), 0, s, p); break;
+    case 64: hipLaunchKernelGGL((object_lds_kernel<St, 64>), gridx, dim3(1024), 0, s, p); break;
+    case 128: hipLaunchKernelGGL((object_lds_kernel<St, 128>), gridx, dim3(1024), 0, s, p); break;
+    default: hipLaunchKernelGGL(object_update_kernel<St>, grid, dim3(256), 0, s, p); break;
+  }
+}
+
 hipError_t launch_object_update(int fp16, const ObjParams& p, hipStream_t s) {
-  if (fp16) hipLaunchKernelGGL(object_update_kernel<StoreF16>, dim3(p.n_tiles), dim3(256), 0, s, p);
-  else hipLaunchKernelGGL(object_update_kernel<StoreF32>, dim3(p.n_tiles), dim3(256), 0, s, p);
+  if (fp16) launch_object_t<StoreF16>(p, s);
+  else launch_object_t<StoreF32>(p, s);
   return hipGetLastError();
 }
 
 hipError_t launch_probe_partial(int fp16, const ProbeParams& p, hipStream_t s) {
-  const dim3 grid((p.N * p.N + 255) / 256, p.G);
+  const dim3 grid(xcd_pad((p.N * p.N + 255) / 256 * p.G));
   if (fp16) hipLaunchKernelGGL(probe_partial_kernel<StoreF16>, grid, dim3(256), 0, s, p);
   else hipLaunchKernelGGL(probe_partial_kernel<StoreF32>, grid, dim3(256), 0, s, p);
   return hipGetLastError();

@@ -506,6 +506,8 @@ __global__ __launch_bounds__(256) void flush_kernel(FlushParams p) {
 // ---------------------------------------------------------------------------
 template <int N, int T, class St, int MODE>
 static void launch_fused_mode(const DivideParams& p, int n_patterns, hipStream_t s) {
+  // plain order: consecutive patterns round-robin over the XCDs measured faster
+  // here than XCD-contiguous ranges (xcd_block)
   hipLaunchKernelGGL((divide_fused_kernel<N, T, St, MODE>), dim3(n_patterns), dim3(T), 0, s, p);
 }
 

@@ -67,7 +67,7 @@ struct ObjParams {
   const int* tile_list;   // ascending scan indices per tile
   float2* obj;
   int H, W, N, tiles_x, n_tiles;
-  float* tile_max;        // [n_tiles] max |O_new|^2 of each tile
+  float* tile_max;        // [object_blocks] max |O_new|^2 of each work-group's tiles
   const float* pmax_part; // [npb] partial maxima of |P|^2
   int npb;
   double tau;
@@ -121,6 +121,8 @@ hipError_t launch_divide(int n, int fp16, const DivideParams& p, int n_patterns,
 hipError_t launch_divide_stage(int n, int fp16, const DivideParams& p, int n_patterns, int stage, hipStream_t s);
 int divide_stages(int n);
 hipError_t launch_object_update(int fp16, const ObjParams& p, hipStream_t s);
+// work-groups of the object launch: each writes one tile_max entry and one metric slice
+int object_blocks(int n, int n_tiles);
 hipError_t launch_probe_partial(int fp16, const ProbeParams& p, hipStream_t s);
 hipError_t launch_flush(int fp16, const FlushParams& p, int J, hipStream_t s);
 hipError_t launch_probe_final(const FinalParams& p, int update_probe, hipStream_t s);
