@@ -95,7 +95,7 @@ Layout make_layout(const pty_scan_desc* d) {
   L.probe = take(nn * 8);
   L.pos = take(J * 8);
   L.tile_off = take((size_t(L.n_tiles) + 1) * 4);
-  L.tile_list = take(size_t(L.max_list) * 4);
+  L.tile_list = take(size_t(L.max_list) * 16);
   L.part = take(3 * size_t(L.G) * nn * 8);
   L.met = take(J * size_t(L.nslot) * MF_COUNT * 8);
   L.met2 = take(size_t(std::max(L.n_tiles, 64)) * MF_COUNT * 8);
@@ -300,7 +300,7 @@ pty_status launch_iteration(pty_scan* s) {
   o.probe = p.probe;
   o.pos = p.pos;
   o.tile_off = s->at<int>(s->L.tile_off);
-  o.tile_list = s->at<int>(s->L.tile_list);
+  o.tile_ent = s->at<int4>(s->L.tile_list);
   o.obj = s->at<float2>(s->L.obj);
   o.H = s->H; o.W = s->W; o.N = s->N;
   o.tiles_x = s->L.tiles_x;
@@ -495,12 +495,16 @@ pty_status create_impl(const pty_scan_desc* d, void* d_ws, size_t ws_bytes, void
       for (int tx = c / kTileW; tx <= (c + N - 1) / kTileW; ++tx) cnt[size_t(ty) * L.tiles_x + tx + 1]++;
   }
   for (int t = 0; t < L.n_tiles; ++t) cnt[t + 1] += cnt[t];
-  std::vector<int> list(std::max(1, cnt[L.n_tiles]));
+  // entries (j, row, col, 0): the concur kernel needs no second lookup of the position
+  std::vector<int> list(4 * size_t(std::max(1, cnt[L.n_tiles])), 0);
   std::vector<int> fillp(cnt.begin(), cnt.end() - 1);
   for (int j = 0; j < J; ++j) {
     const int r = pos[2 * j], c = pos[2 * j + 1];
     for (int ty = r / kTileH; ty <= (r + N - 1) / kTileH; ++ty)
-      for (int tx = c / kTileW; tx <= (c + N - 1) / kTileW; ++tx) list[fillp[size_t(ty) * L.tiles_x + tx]++] = j;
+      for (int tx = c / kTileW; tx <= (c + N - 1) / kTileW; ++tx) {
+        int* e = &list[4 * size_t(fillp[size_t(ty) * L.tiles_x + tx]++)];
+        e[0] = j; e[1] = r; e[2] = c;
+      }
   }
   if (cnt[L.n_tiles] > L.max_list) return fail(PTY_ERR_INVALID_ARG, "internal: tile list bound exceeded");
 
@@ -528,7 +532,7 @@ pty_status create_impl(const pty_scan_desc* d, void* d_ws, size_t ws_bytes, void
   CK(hipMemsetAsync(s->ws, 0, L.total, st), "clear workspace");
   CK(hipMemcpyAsync(s->ws + L.pos, pos.data(), pos.size() * 4, hipMemcpyHostToDevice, st), "positions");
   CK(hipMemcpyAsync(s->ws + L.tile_off, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice, st), "tile offsets");
-  CK(hipMemcpyAsync(s->ws + L.tile_list, list.data(), size_t(cnt[L.n_tiles]) * 4, hipMemcpyHostToDevice, st),
+  CK(hipMemcpyAsync(s->ws + L.tile_list, list.data(), size_t(cnt[L.n_tiles]) * 16, hipMemcpyHostToDevice, st),
      "tile lists");
   std::vector<float2> tw(N);
   for (int m = 0; m < N; ++m) {

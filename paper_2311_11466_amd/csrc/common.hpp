@@ -153,11 +153,27 @@ __device__ __forceinline__ void dft4x4_reg(float2 (&v)[NV]) {
 // ---------------------------------------------------------------------------
 // exit-wave storage formats
 // ---------------------------------------------------------------------------
+// Raw buffer resource over `bytes` bytes from p (gfx9 family: stride 0, word 3
+// = 0x00020000).  A load through it at a byte offset at or past `bytes`
+// returns zero and makes no memory request; kOutside is such an offset.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kOutside = 0x7fffffff;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ float2 buffer_load_f2(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+  return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+
 struct StoreF32 {
   using elem = float2;
   static constexpr int kFormat = 0;
   __device__ __forceinline__ static float2 load(const elem* p, size_t i, float /*inv_scale*/) { return p[i]; }
   __device__ __forceinline__ static void store(elem* p, size_t i, float2 v, float /*scale*/) { p[i] = v; }
+  __device__ __forceinline__ static float2 load_buf(__amdgpu_buffer_rsrc_t r, int byte_off, float /*inv*/) {
+    return buffer_load_f2(r, byte_off);
+  }
 };
 
 // complex float16 times a power-of-two scale (round to nearest even)
@@ -170,6 +186,13 @@ struct StoreF16 {
   }
   __device__ __forceinline__ static void store(elem* p, size_t i, float2 v, float scale) {
     p[i] = __float22half2_rn(make_float2(v.x * scale, v.y * scale));
+  }
+  __device__ __forceinline__ static float2 load_buf(__amdgpu_buffer_rsrc_t r, int byte_off, float inv_scale) {
+    const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
+    __half2 h;
+    __builtin_memcpy(&h, &v, 4);
+    const float2 f = __half22float2(h);
+    return make_float2(f.x * inv_scale, f.y * inv_scale);
   }
 };
 

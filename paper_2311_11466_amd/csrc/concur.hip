@@ -73,78 +73,83 @@ __global__ __launch_bounds__(256) void metric_slice_kernel(MetricParams p) {
   metric_slice<256>(p, blockIdx.x, red);
 }
 
-// One work-group per 64 x 16 object tile; a thread owns one column and four
-// rows (row0 + 4 i).  The tile's list of overlapping positions is staged in
-// LDS (in chunks of kListChunk), then consumed kUnroll entries at a time so
-// that each thread keeps 4 * kUnroll exit-wave loads in flight.
+// One work-group per 64 x 16 object tile (N = 256, whose probe does not fit
+// in LDS); a thread owns one column and four rows (row0 + 4 i).  The tile's
+// list entries are staged in LDS (in chunks of kListChunk).  Exit waves and
+// probe are read through buffer resources covering one pattern and the
+// probe: a pixel outside the window gets an out-of-range offset, which reads
+// zero without a memory request, so it adds exactly zero.  The next entry's
+// requests are in flight while the current one is accumulated.
 constexpr int kListChunk = 256;
-constexpr int kUnroll = 4;
 
 template <class St>
 __global__ __launch_bounds__(256) void object_update_kernel(ObjParams p) {
   __shared__ float red[4];
   __shared__ int4 ent[kListChunk];     // (scan index, row offset, col offset, unused)
-  const int tile = blockIdx.x;
+  __shared__ double mred[MF_COUNT * 4];
+  const int tile = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
+  if (tile >= p.n_tiles) return;
   const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = tx * kTileW + lane;
   const int row0 = ty * kTileH + wave;
   const int N = p.N;
-  const size_t NN = size_t(N) * N;
+  const int NN = N * N;
   using elem = typename St::elem;
   const elem* ys = reinterpret_cast<const elem*>(p.y);
 
+  metric_slice<256>(p.mp, tile, mred);
+  const int e0 = p.tile_off[tile], e1 = p.tile_off[tile + 1];
   float pm = 0.0f;
   for (int i = threadIdx.x; i < p.npb; i += 256) pm = fmaxf(pm, p.pmax_part[i]);
+  float2 oldo[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = row0 + 4 * i;
+    oldo[i] = (row < p.H && col < p.W) ? p.obj[size_t(row) * p.W + col] : make_float2(0.f, 0.f);
+  }
   pm = block_max<256>(pm, red);
   const double thr = p.tau * double(pm);
 
   double nr[4] = {0, 0, 0, 0}, ni[4] = {0, 0, 0, 0}, dd[4] = {0, 0, 0, 0};
-  const int e0 = p.tile_off[tile], e1 = p.tile_off[tile + 1];
+  const __amdgpu_buffer_rsrc_t prs = buffer_rsrc(p.probe, NN * 8);
+  auto issue = [&](int e, int cn, float2 (&pv)[4], float2 (&yv)[4]) {
+    const int4 en = ent[min(e, cn - 1)];
+    const int du = col - en.z;
+    const int dr = row0 - en.y;
+    const bool cin = e < cn && (unsigned)du < (unsigned)N;
+    const int base = dr * N + du;
+    const int j = __builtin_amdgcn_readfirstlane(en.x);       // one entry per wave
+    const __amdgpu_buffer_rsrc_t yrs = buffer_rsrc(ys + size_t(j) * NN, NN * int(sizeof(elem)));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool ok = cin && (unsigned)(dr + 4 * i) < (unsigned)N;
+      const int u = base + 4 * N * i;
+      pv[i] = buffer_load_f2(prs, ok ? u * 8 : kOutside);
+      yv[i] = St::load_buf(yrs, ok ? u * int(sizeof(elem)) : kOutside, p.inv_scale);
+    }
+  };
+  auto accumulate = [&](const float2 (&pv)[4], const float2 (&yv)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double px = pv[i].x, py = pv[i].y, yx = yv[i].x, yy = yv[i].y;
+      nr[i] = fma(px, yx, fma(py, yy, nr[i]));
+      ni[i] = fma(px, yy, fma(-py, yx, ni[i]));
+      dd[i] = fma(px, px, fma(py, py, dd[i]));
+    }
+  };
   for (int c0 = e0; c0 < e1; c0 += kListChunk) {
     const int cn = min(kListChunk, e1 - c0);
     __syncthreads();
-    for (int i = threadIdx.x; i < cn; i += 256) {
-      const int j = p.tile_list[c0 + i];
-      const int2 pj = p.pos[j];
-      ent[i] = make_int4(j, pj.x, pj.y, 0);
-    }
+    for (int i = threadIdx.x; i < cn; i += 256) ent[i] = p.tile_ent[c0 + i];
     __syncthreads();
-    // Branch-free: indices are clamped into the window (valid addresses, the
-    // same rows and lines the in-window lanes fetch) and masked values are
-    // zeroed, so a group of loads issues back to back.
-    int e = 0;
-    for (; e < cn; e += kUnroll) {
-      float2 pv[kUnroll][4], yv[kUnroll][4];
-#pragma unroll
-      for (int q = 0; q < kUnroll; ++q) {
-        const int4 en = ent[min(e + q, cn - 1)];
-        const bool live = e + q < cn;
-        const int u1 = col - en.z;
-        const bool cin = live && (unsigned)u1 < (unsigned)N;
-        const int u1c = min(max(u1, 0), N - 1);
-        const elem* yj = ys + size_t(en.x) * NN;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int u0 = row0 + 4 * i - en.y;
-          const bool ok = cin && (unsigned)u0 < (unsigned)N;
-          const int u = min(max(u0, 0), N - 1) * N + u1c;
-          const float2 a = p.probe[u];
-          const float2 b = St::load(yj, u, p.inv_scale);
-          pv[q][i] = make_float2(ok ? a.x : 0.f, ok ? a.y : 0.f);
-          yv[q][i] = make_float2(ok ? b.x : 0.f, ok ? b.y : 0.f);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kUnroll; ++q) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const double px = pv[q][i].x, py = pv[q][i].y, yx = yv[q][i].x, yy = yv[q][i].y;
-          nr[i] += px * yx + py * yy;
-          ni[i] += px * yy - py * yx;
-          dd[i] += px * px + py * py;
-        }
-      }
+    float2 pa[4], ya[4], pb[4], yb[4];
+    issue(0, cn, pa, ya);
+    for (int e = 0; e < cn; e += 2) {
+      issue(e + 1, cn, pb, yb);
+      accumulate(pa, ya);
+      if (e + 2 < cn) issue(e + 2, cn, pa, ya);
+      accumulate(pb, yb);
     }
   }
   float m = 0.0f;
@@ -152,35 +157,32 @@ __global__ __launch_bounds__(256) void object_update_kernel(ObjParams p) {
   for (int i = 0; i < 4; ++i) {
     const int row = row0 + 4 * i;
     if (row < p.H && col < p.W) {
-      const size_t idx = size_t(row) * p.W + col;
-      float2 o = p.obj[idx];
+      float2 o = oldo[i];
       if (dd[i] > thr) {
         o = make_float2(float(nr[i] / dd[i]), float(ni[i] / dd[i]));
-        p.obj[idx] = o;
+        p.obj[size_t(row) * p.W + col] = o;
       }
       m = fmaxf(m, cnorm(o));
     }
   }
   m = block_max<256>(m, red);
   if (threadIdx.x == 0) p.tile_max[tile] = m;
-  __shared__ double mred[MF_COUNT * 4];
-  metric_slice<256>(p.mp, tile, mred);
 }
 
 // N <= 128: the probe (at most 128 KiB) is staged in LDS once per work-group
 // and the work-group of 1024 threads owns kGroupTiles tiles, one per 256
-// threads, with the same per-thread arithmetic and order as above; the
-// probe gathers then cost LDS reads instead of cache traffic.  Tile maxima
-// and metric slices are per work-group.
+// threads, summing in the same list order as above.  A pixel outside the
+// window takes its probe factor from a zero entry after the probe in LDS and
+// its exit wave through an out-of-range buffer offset (zero, no memory
+// request), so it adds exactly zero.  Tile maxima and metric slices are per
+// work-group.
 constexpr int kGroupTiles = 4;
-#ifndef PTY_LDS_UNROLL
-#define PTY_LDS_UNROLL 2
-#endif
-constexpr int kLdsUnroll = PTY_LDS_UNROLL;   // 1024 threads: at most 128 VGPRs each
 
 template <class St, int N>
 __global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
-  __shared__ float2 pl[N * N];
+  constexpr int NN = N * N;
+  constexpr int kZero = NN;            // index of the zero probe entry
+  __shared__ float2 pl[NN + 1];
   __shared__ int4 ent[kGroupTiles][kListChunk];
   __shared__ float red[16];
   __shared__ int cnt[kGroupTiles];
@@ -195,65 +197,79 @@ __global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
   const int lane = lt & 63, wave = lt >> 6;
   const int col = tx * kTileW + lane;
   const int row0 = ty * kTileH + wave;
-  constexpr size_t NN = size_t(N) * N;
   using elem = typename St::elem;
   const elem* ys = reinterpret_cast<const elem*>(p.y);
 
-  for (int i = threadIdx.x; i < N * N; i += 1024) pl[i] = p.probe[i];
+  // ---- the block's independent reads, requested together: metric slice,
+  // list bounds, probe, probe maxima, the old object values -----------------
+  metric_slice<1024>(p.mp, blk, mred);
+  const int e0 = p.tile_off[tc];
+  const int len = tile_ok ? p.tile_off[tc + 1] - e0 : 0;
+  float2 pst[NN / 1024];
+#pragma unroll
+  for (int k = 0; k < NN / 1024; ++k) pst[k] = p.probe[threadIdx.x + 1024 * k];
   float pm = 0.0f;
   for (int i = threadIdx.x; i < p.npb; i += 1024) pm = fmaxf(pm, p.pmax_part[i]);
-  pm = block_max<1024>(pm, red);      // its barriers also publish pl
-  const double thr = p.tau * double(pm);
-
-  const int e0 = tile_ok ? p.tile_off[tile] : 0;
-  const int len = tile_ok ? p.tile_off[tile + 1] - e0 : 0;
+  float2 oldo[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = row0 + 4 * i;
+    const bool in = tile_ok && row < p.H && col < p.W;
+    oldo[i] = in ? p.obj[size_t(row) * p.W + col] : make_float2(0.f, 0.f);
+  }
   if (lt == 0) cnt[g] = len;
-  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NN / 1024; ++k) pl[threadIdx.x + 1024 * k] = pst[k];
+  if (threadIdx.x == 0) pl[kZero] = make_float2(0.f, 0.f);
+  pm = block_max<1024>(pm, red);      // its barriers also publish pl and cnt
+  const double thr = p.tau * double(pm);
   int maxlen = cnt[0];
 #pragma unroll
   for (int q = 1; q < kGroupTiles; ++q) maxlen = max(maxlen, cnt[q]);
 
   double nr[4] = {0, 0, 0, 0}, ni[4] = {0, 0, 0, 0}, dd[4] = {0, 0, 0, 0};
+  // requests for entry e (past the end of the list: the last entry with a
+  // zero probe): exit waves from memory, probe factors from LDS
+  auto issue = [&](int e, int cn, float2 (&pv)[4], float2 (&yv)[4]) {
+    const int4 en = ent[g][min(e, cn - 1)];
+    const int du = col - en.z;                 // column in the window
+    const int dr = row0 - en.y;                // row in the window of pixel 0
+    const bool cin = e < cn && (unsigned)du < (unsigned)N;
+    const int base = dr * N + du;
+    const int j = __builtin_amdgcn_readfirstlane(en.x);       // one entry per wave
+    const __amdgpu_buffer_rsrc_t yrs = buffer_rsrc(ys + size_t(j) * NN, NN * int(sizeof(elem)));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool ok = cin && (unsigned)(dr + 4 * i) < (unsigned)N;
+      const int u = base + 4 * N * i;
+      pv[i] = pl[ok ? u : kZero];
+      yv[i] = St::load_buf(yrs, ok ? u * int(sizeof(elem)) : kOutside, p.inv_scale);
+    }
+  };
+  auto accumulate = [&](const float2 (&pv)[4], const float2 (&yv)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double px = pv[i].x, py = pv[i].y, yx = yv[i].x, yy = yv[i].y;
+      nr[i] = fma(px, yx, fma(py, yy, nr[i]));
+      ni[i] = fma(px, yy, fma(-py, yx, ni[i]));
+      dd[i] = fma(px, px, fma(py, py, dd[i]));
+    }
+  };
   for (int c0 = 0; c0 < maxlen; c0 += kListChunk) {   // same trip count in every group
     const int cn = min(kListChunk, len - c0);
     __syncthreads();
-    for (int i = lt; i < cn; i += 256) {
-      const int j = p.tile_list[e0 + c0 + i];
-      const int2 pj = p.pos[j];
-      ent[g][i] = make_int4(j, pj.x, pj.y, 0);
-    }
+    for (int i = lt; i < cn; i += 256) ent[g][i] = p.tile_ent[e0 + c0 + i];
     __syncthreads();
-    for (int e = 0; e < cn; e += kLdsUnroll) {
-      float2 pv[kLdsUnroll][4], yv[kLdsUnroll][4];
-#pragma unroll
-      for (int q = 0; q < kLdsUnroll; ++q) {
-        const int4 en = ent[g][min(e + q, cn - 1)];
-        const bool live = e + q < cn;
-        const int u1 = col - en.z;
-        const bool cin = live && (unsigned)u1 < (unsigned)N;
-        const int u1c = min(max(u1, 0), N - 1);
-        const elem* yj = ys + size_t(en.x) * NN;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int u0 = row0 + 4 * i - en.y;
-          const bool ok = cin && (unsigned)u0 < (unsigned)N;
-          const int u = min(max(u0, 0), N - 1) * N + u1c;
-          const float2 a = pl[u];
-          const float2 b = St::load(yj, u, p.inv_scale);
-          pv[q][i] = make_float2(ok ? a.x : 0.f, ok ? a.y : 0.f);
-          yv[q][i] = make_float2(ok ? b.x : 0.f, ok ? b.y : 0.f);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kLdsUnroll; ++q) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const double px = pv[q][i].x, py = pv[q][i].y, yx = yv[q][i].x, yy = yv[q][i].y;
-          nr[i] += px * yx + py * yy;
-          ni[i] += px * yy - py * yx;
-          dd[i] += px * px + py * py;
-        }
-      }
+    if (cn <= 0) continue;
+    // two register sets: the next entry's requests are in flight while the
+    // current one is accumulated (deeper rings measured slower)
+    float2 pa[4], ya[4], pb[4], yb[4];
+    issue(0, cn, pa, ya);
+    for (int e = 0; e < cn; e += 2) {
+      issue(e + 1, cn, pb, yb);
+      accumulate(pa, ya);
+      if (e + 2 < cn) issue(e + 2, cn, pa, ya);
+      accumulate(pb, yb);
     }
   }
   float m = 0.0f;
@@ -261,18 +277,16 @@ __global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
   for (int i = 0; i < 4; ++i) {
     const int row = row0 + 4 * i;
     if (tile_ok && row < p.H && col < p.W) {
-      const size_t idx = size_t(row) * p.W + col;
-      float2 o = p.obj[idx];
+      float2 o = oldo[i];
       if (dd[i] > thr) {
         o = make_float2(float(nr[i] / dd[i]), float(ni[i] / dd[i]));
-        p.obj[idx] = o;
+        p.obj[size_t(row) * p.W + col] = o;
       }
       m = fmaxf(m, cnorm(o));
     }
   }
   m = block_max<1024>(m, red);
   if (threadIdx.x == 0) p.tile_max[blk] = m;
-  metric_slice<1024>(p.mp, blk, mred);
 }
 
 constexpr int kProbeUnroll = 8;
@@ -403,12 +417,11 @@ int object_blocks(int n, int n_tiles) {
 
 template <class St>
 static void launch_object_t(const ObjParams& p, hipStream_t s) {
-  const dim3 grid(object_blocks(p.N, p.n_tiles));
-  const dim3 gridx(xcd_pad(object_blocks(p.N, p.n_tiles)));
+  const dim3 grid(xcd_pad(object_blocks(p.N, p.n_tiles)));
   switch (p.N) {
-    case 32: hipLaunchKernelGGL((object_lds_kernel<St, 32>), gridx, dim3(1024), 0, s, p); break;
-    case 64: hipLaunchKernelGGL((object_lds_kernel<St, 64>), gridx, dim3(1024), 0, s, p); break;
-    case 128: hipLaunchKernelGGL((object_lds_kernel<St, 128>), gridx, dim3(1024), 0, s, p); break;
+    case 32: hipLaunchKernelGGL((object_lds_kernel<St, 32>), grid, dim3(1024), 0, s, p); break;
+    case 64: hipLaunchKernelGGL((object_lds_kernel<St, 64>), grid, dim3(1024), 0, s, p); break;
+    case 128: hipLaunchKernelGGL((object_lds_kernel<St, 128>), grid, dim3(1024), 0, s, p); break;
     default: hipLaunchKernelGGL(object_update_kernel<St>, grid, dim3(256), 0, s, p); break;
   }
 }

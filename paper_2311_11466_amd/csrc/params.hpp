@@ -64,7 +64,7 @@ struct ObjParams {
   const float2* probe;
   const int2* pos;
   const int* tile_off;    // [n_tiles + 1]
-  const int* tile_list;   // ascending scan indices per tile
+  const int4* tile_ent;   // per tile, ascending j: (j, row, col, 0) of each overlapping window
   float2* obj;
   int H, W, N, tiles_x, n_tiles;
   float* tile_max;        // [object_blocks] max |O_new|^2 of each work-group's tiles
