@@ -175,13 +175,19 @@ def concur_probe(y, obj, probe, pos, tau=DEFAULT_TAU):
     return out
 
 
-def concur(y, obj, probe, pos, tau=DEFAULT_TAU, update_probe=True):
+def concur(y, obj, probe, pos, tau=DEFAULT_TAU, update_probe=True, sweeps=1):
     """P_C y: object step, then (blind) probe step, then re-extract the exit waves.
 
+    ``sweeps`` repeats the (object, probe) pair with the same y, each object
+    step from the previous sweep's probe (alternating least squares on the
+    bilinear consensus; the reading with one sweep is the default).
     Returns (z, O_new, P_new) with z_j = P_new * S_j O_new.
     """
-    obj_new = concur_object(y, obj, probe, pos, tau)
-    probe_new = concur_probe(y, obj_new, probe, pos, tau) if update_probe else np.array(probe)
+    obj_new, probe_new = obj, np.array(probe)
+    for _ in range(int(sweeps)):
+        obj_new = concur_object(y, obj_new, probe_new, pos, tau)
+        if update_probe:
+            probe_new = concur_probe(y, obj_new, probe_new, pos, tau)
     return exit_waves(obj_new, probe_new, pos), obj_new, probe_new
 
 
@@ -207,7 +213,7 @@ def init_state(obj0, probe0, pos) -> State:
 
 
 def step(state: State, amp, pos, a, b, c, blind=True, tau=DEFAULT_TAU,
-         probe_update_start=0):
+         probe_update_start=0, sweeps=1):
     """One generalised iteration from (x_k, O_k, P_k).
 
     Returns (new_state, info) where info holds y = P^c_D x_k, z = P_C y and the
@@ -222,7 +228,7 @@ def step(state: State, amp, pos, a, b, c, blind=True, tau=DEFAULT_TAU,
         return modulus_projection(x, amp)
 
     def concur_op(y):
-        z, o, p = concur(y, state.obj, state.probe, pos, tau, update_probe)
+        z, o, p = concur(y, state.obj, state.probe, pos, tau, update_probe, sweeps)
         out["obj"], out["probe"], out["z"] = o, p, z
         return z
 
@@ -248,6 +254,23 @@ def run(state: State, amp, pos, a, b, c, n_iter, **kw) -> State:
     for _ in range(n_iter):
         state, _ = step(state, amp, pos, a, b, c, **kw)
     return state
+
+
+def run_schedule(state: State, amp, pos, abcs, **kw) -> State:
+    """Iteration-dependent relaxation: iteration i uses abcs[i] = (a_i, b_i, c_i)."""
+    for a, b, c in abcs:
+        state, _ = step(state, amp, pos, a, b, c, **kw)
+    return state
+
+
+def shadow(state: State, amp, pos, blind=True, tau=DEFAULT_TAU, sweeps=1):
+    """The shadow estimate P_C(P_D x_k): the consensus (O, P) of the unrelaxed
+    divide of the current iterate, warm started from the state's (O, P).  At a
+    fixed point of the DR family the solution is P_D x*, so this is the
+    estimate to report there; the state is not changed."""
+    y = modulus_projection(state.x, np.asarray(amp, dtype=np.float64))
+    _, o, p = concur(y, state.obj, state.probe, pos, tau, bool(blind), sweeps)
+    return o, p
 
 
 # --------------------------------------------------------------------------

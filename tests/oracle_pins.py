@@ -202,6 +202,52 @@ def pin_concur_projection_properties():
     assert f(o1, p1) <= f(o1, probe) + 1e-12
 
 
+def pin_concur_sweeps_alternating_least_squares():
+    """K sweeps: sum_j |P S_j O - y_j|^2 never increases from sweep to sweep;
+    for exit waves that some (O*, P*) explains exactly, the sweeps from a
+    perturbed start drive it to zero (each sweep must use the previous
+    sweep's probe and object)."""
+    h, w, n, pos, probe, obj, y = _tiny_problem(11)
+
+    def f(o, p, target):
+        return np.sum(np.abs(po.exit_waves(o, p, pos) - target) ** 2)
+    vals = []
+    for k in range(1, 7):
+        _, o, p = po.concur(y, obj, probe, pos, update_probe=True, sweeps=k)
+        vals.append(f(o, p, y))
+    assert all(b <= a + 1e-12 for a, b in zip(vals, vals[1:])), vals
+    assert vals[-1] < vals[0]
+    rng = _rng(14)
+    y_exact = po.exit_waves(obj, probe, pos)
+    o0 = obj + 0.3 * _crandn(rng, *obj.shape)
+    p0 = probe + 0.3 * _crandn(rng, *probe.shape)
+    _, o, p = po.concur(y_exact, o0, p0, pos, update_probe=True, sweeps=200)
+    assert f(o, p, y_exact) <= 1e-10 * f(o0, p0, y_exact)
+    # the known-probe consensus is a projection: more sweeps change nothing
+    _, o1, _ = po.concur(y, obj, probe, pos, update_probe=False, sweeps=1)
+    _, o3, _ = po.concur(y, obj, probe, pos, update_probe=False, sweeps=3)
+    assert np.allclose(o1, o3, rtol=1e-12, atol=1e-12)
+
+
+def pin_shadow_recovers_the_true_state():
+    """Noise-free data and the true exit waves: P_D leaves x unchanged and the
+    consensus of the true exit waves is the true (O, P), so the shadow is the
+    truth; from a perturbed start it is an unrelaxed divide plus consensus,
+    i.e. one DC step's (O, P)."""
+    h, w, n, pos, probe, obj, _ = _tiny_problem(12)
+    amp = np.abs(po.dft2(po.exit_waves(obj, probe, pos)))
+    st = po.init_state(obj, probe, pos)
+    o, p = po.shadow(st, amp, pos)
+    assert np.allclose(o, obj, rtol=1e-10, atol=1e-10)
+    assert np.allclose(p, probe, rtol=1e-10, atol=1e-10)
+    rng = _rng(13)
+    st2 = po.State(st.x + 0.1 * _crandn(rng, *st.x.shape), obj * 0.9, probe, 0)
+    o2, p2 = po.shadow(st2, amp, pos)
+    new, _ = po.step(st2, amp, pos, 1.0, 1.0, 1.0)
+    assert np.allclose(o2, new.obj, rtol=1e-12, atol=1e-12)
+    assert np.allclose(p2, new.probe, rtol=1e-12, atol=1e-12)
+
+
 # --------------------------------------------------------------------------
 # The generalised iteration
 # --------------------------------------------------------------------------
@@ -301,6 +347,8 @@ ALL_PINS = [
     pin_probe_step_is_least_squares,
     pin_concur_is_average_in_the_plain_case,
     pin_concur_projection_properties,
+    pin_concur_sweeps_alternating_least_squares,
+    pin_shadow_recovers_the_true_state,
     pin_three_circle_worked_example,
     pin_presets_match_textbook_updates,
 ]

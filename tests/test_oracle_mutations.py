@@ -114,6 +114,20 @@ def _preset_raar_wrong(name, param=0.0):
 
 _orig_preset = po.preset
 
+
+def _concur_stale_probe(y, obj, probe, pos, tau=po.DEFAULT_TAU, update_probe=True, sweeps=1):
+    obj_new, probe_new = obj, np.array(probe)
+    for _ in range(int(sweeps)):
+        obj_new = po.concur_object(y, obj_new, probe, pos, tau)    # slip: first probe every sweep
+        if update_probe:
+            probe_new = po.concur_probe(y, obj_new, probe_new, pos, tau)
+    return po.exit_waves(obj_new, probe_new, pos), obj_new, probe_new
+
+
+def _shadow_no_divide(state, amp, pos, blind=True, tau=po.DEFAULT_TAU, sweeps=1):
+    _, o, p = po.concur(state.x, state.obj, state.probe, pos, tau, bool(blind), sweeps)  # slip: P_D skipped
+    return o, p
+
 MUTATIONS = {
     "object_no_conj": [("concur_object", _obj_no_conj)],
     "probe_no_conj": [("concur_probe", _probe_no_conj)],
@@ -128,6 +142,8 @@ MUTATIONS = {
     "exit_wave_conj_probe": [("exit_waves", _exit_conj_probe)],
     "preset_ar": [("preset", _preset_ar_wrong)],
     "preset_raar": [("preset", _preset_raar_wrong)],
+    "concur_sweeps_stale_probe": [("concur", _concur_stale_probe)],
+    "shadow_without_divide": [("shadow", _shadow_no_divide)],
 }
 
 
