@@ -58,3 +58,18 @@ def test_aligned_error_removes_global_scale():
     t = rng.standard_normal((5, 5)) + 1j * rng.standard_normal((5, 5))
     assert po.aligned_error((0.3 - 2j) * t, t) < 1e-28
     assert po.aligned_error(t + 1, t) > 1e-3
+
+
+def test_aligned_error_is_the_minimum_over_complex_scale():
+    """The closed-form scale agrees with a numerical minimisation over g."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(21)
+    t = rng.standard_normal((12, 9)) + 1j * rng.standard_normal((12, 9))
+    e = t * (0.7 + 0.2j) + 0.3 * (rng.standard_normal(t.shape) + 1j * rng.standard_normal(t.shape))
+
+    def f(v):
+        g = v[0] + 1j * v[1]
+        return float(np.sum(np.abs(t - g * e) ** 2) / np.sum(np.abs(t) ** 2))
+    best = minimize(f, [0.0, 0.0], method="Nelder-Mead", options={"xatol": 1e-12, "fatol": 1e-15}).fun
+    assert abs(po.aligned_error(e, t) - best) <= 1e-9
+    assert po.aligned_error(e, t) <= f([1.0, 0.0])
