@@ -143,12 +143,25 @@ def bench(args):
                 torch.as_tensor(scan.probe0.astype(np.complex64)).to(dev),
                 storage=args.storage, blind=True, device=dev, full_metrics=full_metrics)
     g.set_algorithm(*abc)
-    g.iterate(args.warmup)
+    g.set_concur_sweeps(args.concur_sweeps)
+    sched = None
+    if args.schedule == "linear":
+        # the preset's parameter (beta or lambda) moves linearly from --param to
+        # --param-end over warm-up and timed iterations
+        n_all = args.warmup + args.steps
+        sched = [pk.preset(args.algorithm, args.param + (args.param_end - args.param) * i / max(n_all - 1, 1))
+                 for i in range(n_all)]
+        g.iterate_schedule(sched[:args.warmup])
+    else:
+        g.iterate(args.warmup)
     torch.cuda.synchronize()
     g.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    g.iterate(args.steps)
+    if sched is not None:
+        g.iterate_schedule(sched[args.warmup:])
+    else:
+        g.iterate(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = g.profile_read()
@@ -215,6 +228,9 @@ def bench(args):
                                else "fourier error every iteration"),
                    "exit_wave_state": "w = (1-a) x + a(1-b) y" if pk.uses_blend_form(cfg.n, abc[0], abc[1],
                                                                                      full_metrics) else "x",
+                   "concur_sweeps": args.concur_sweeps,
+                   "schedule": (f"{args.algorithm} parameter linear {args.param} -> {args.param_end}"
+                                if sched is not None else "constant"),
                    "photons": cfg.photons, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -273,6 +289,109 @@ def bench_served(args):
                    "peak_active": s["peak_active"], "peak_workspace_gb": round(s["peak_workspace_bytes"] / 1e9, 2)},
         "iterations": [r.iterations for r in opened.results],
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_sp(args):
+    """Sequential projections on the same scan: one step = one SP iteration
+    (every position once, in ascending order, batched by dependency level)."""
+    import numpy as np
+    import torch
+    import paper_2311_11466_amd as pk
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    scan = make_workload(args.workload)
+    cfg = scan.config
+    g = pk.Scan(torch.as_tensor(scan.pos).to(dev), torch.as_tensor(scan.intensity).to(dev),
+                torch.as_tensor(scan.obj0.astype(np.complex64)).to(dev),
+                torch.as_tensor(scan.probe0.astype(np.complex64)).to(dev), blind=True, device=dev)
+    nb = 0
+    for _ in range(args.warmup):
+        nb = g.sp_iterate(None, args.sp_max_batch, args.sp_alpha, args.sp_beta)
+    torch.cuda.synchronize()
+    g.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.sp_iterate(None, args.sp_max_batch, args.sp_alpha, args.sp_beta)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = g.profile_read()
+    m = g.metrics(allow_diverged=True)
+    g.close()
+    nn = cfg.n * cfg.n
+    per_batch = scan.n_pos / max(nb, 1)
+    bytes_per = {"divide": 20 * nn * per_batch, "probe": 8 * nn * per_batch + 16 * nn}
+    names = {"divide": "divide_fused_kernel (sequential-projection mode)", "probe": "sp_probe_kernel"}
+    kernels = {}
+    for k, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        avg_us = ms / cnt * 1e3
+        b = bytes_per.get(k)
+        kernels[names.get(k, k)] = {"avg_us": round(avg_us, 3), "launches": cnt, "share": round(ms / (dt * 1e3), 4),
+                                    "algorithmic_bytes": round(b) if b else None,
+                                    "GBs": round(b / (avg_us * 1e-6) / 1e9, 1) if b else None}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+    d = kernels[dom]
+    line = {
+        "metric": "diffraction-pattern projections/s (sequential projections) at 1 GPU",
+        "value": round(scan.n_pos * args.steps / dt, 1),
+        "unit": "projections/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": cfg.name, "method": "sequential projections", "positions": scan.n_pos, "n": cfg.n,
+                   "batches_per_iteration": nb, "max_batch": args.sp_max_batch,
+                   "alpha": args.sp_alpha, "beta": args.sp_beta, "blind": True},
+        "roofline": {"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(d["GBs"] / HBM_PEAK_GBS, 4) if d["GBs"] else None, "traffic": None,
+                     "kernel": dom, "avg_us": d["avg_us"]},
+        "kernels": kernels,
+        "metrics_last": m,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_compare(args):
+    """Algorithm comparison (error lines of the presets, big and small probe).
+
+    args.steps iterations per algorithm from the standard start; per algorithm
+    the mean object error (against the truth, global complex scale removed) and
+    Fourier error over the last 20 iterations, the ranking by object error and
+    the uninstrumented time per iteration.  Full curves go to --curves-out.
+    """
+    import numpy as np
+    import torch
+    from ptysynth import make_scan, comparison_config
+    from paper_2311_11466_amd.compare import error_lines, summary
+    torch.cuda.set_device(0)
+    result, curves = {}, {}
+    for probe in ("big", "small"):
+        cfg = comparison_config(probe)
+        sc = make_scan(cfg, intensity_dtype=np.float32)
+        t0 = time.perf_counter()
+        lines = error_lines(sc.pos, sc.intensity, sc.obj0, sc.probe0, sc.obj_true, sc.metric_box(),
+                            n_iter=args.steps, sweeps=args.concur_sweeps)
+        print(f"# {cfg.name}: {len(lines)} algorithms x {args.steps} iterations in "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        result[probe] = summary(lines)
+        result[probe]["config"] = {"object": [cfg.obj_h, cfg.obj_w], "n": cfg.n, "positions": sc.n_pos,
+                                   "probe_radius": cfg.probe_radius, "step": cfg.step, "photons": cfg.photons,
+                                   "error_box": list(sc.metric_box())}
+        curves[probe] = lines
+    line = {
+        "metric": "error lines of the presets: object error vs truth and Fourier error per iteration",
+        "config": {"workload": "compare (big and small probe)", "iterations": args.steps,
+                   "concur_sweeps": args.concur_sweeps, "storage": "fp32", "blind": True},
+        "data": "synthetic",
+        "big": result["big"],
+        "small": result["small"],
+    }
+    if args.curves_out:
+        with open(args.curves_out, "w") as fh:
+            json.dump(curves, fh)
     print(json.dumps(line), flush=True)
 
 
@@ -335,7 +454,17 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="scan_n128",
-                    choices=["scan_n128", "large_n256", "tiny_n32", "served"])
+                    choices=["scan_n128", "large_n256", "tiny_n32", "served", "compare"])
+    ap.add_argument("--curves-out", default=None, help="compare: write the full error lines here (JSON)")
+    ap.add_argument("--method", default="abc", choices=["abc", "sp"],
+                    help="abc: the generalised iteration; sp: sequential projections")
+    ap.add_argument("--sp-max-batch", type=int, default=0)
+    ap.add_argument("--sp-alpha", type=float, default=1.0)
+    ap.add_argument("--sp-beta", type=float, default=1.0)
+    ap.add_argument("--concur-sweeps", type=int, default=1, help="(object, probe) sweeps per concur step")
+    ap.add_argument("--schedule", default="constant", choices=["constant", "linear"],
+                    help="linear: the preset parameter moves from --param to --param-end")
+    ap.add_argument("--param-end", type=float, default=0.3)
     ap.add_argument("--metrics", default="all", choices=["all", "fourier"],
                     help="all: Fourier, consistency and change errors every iteration; "
                          "fourier: the Fourier error only (enables the blend form)")
@@ -361,6 +490,10 @@ def main():
         sys.exit(2)
     if args.workload == "served":
         bench_served(args)
+    elif args.workload == "compare":
+        bench_compare(args)
+    elif args.method == "sp":
+        bench_sp(args)
     else:
         bench(args)
 

@@ -147,6 +147,70 @@ pty_status pty_iterate(pty_scan *scan, int32_t n);
  * it alone. */
 pty_status pty_iterate_many(pty_scan *const *scans, int32_t count, int32_t n);
 
+/* Iteration-dependent relaxation (Introduction: the relaxation of a
+ * projection may change as the iteration proceeds).  Runs n iterations,
+ * iteration i with (a, b, c) = (abc[3i], abc[3i+1], abc[3i+2]); abc is a host
+ * array of 3n doubles.  Every entry is checked (finite, a != 0) before any
+ * work is queued: PTY_ERR_INVALID_ARG leaves the scan unchanged.  The last
+ * entry stays the scan's (a, b, c) afterwards.  Asynchronous like
+ * pty_iterate. */
+pty_status pty_iterate_schedule(pty_scan *scan, const double *abc, int32_t n);
+
+/* Number of (object, probe) sweeps of the concur step per iteration (1 to
+ * 64; default 1).  The blind concur is a least-squares consensus over two
+ * bilinear factors; with K sweeps the object step (from the current probe)
+ * and the probe step (from the new object) are repeated K times on the same
+ * divided exit waves, each sweep starting from the previous one.  Without
+ * probe updates one object step is exact and K is ignored. */
+pty_status pty_set_concur_sweeps(pty_scan *scan, int32_t sweeps);
+
+/* Shadow estimate P_C(P_D x_k) of the current iterate: the unrelaxed divide
+ * of x_k followed by the consensus (with the scan's sweeps, the probe updated
+ * as in the next iteration would update it), warm started from the scan's
+ * (O, P).  At a fixed point of the Douglas-Rachford family the solution is
+ * P_D x*, so this is the estimate to report there (Conclusion's comparison of
+ * those algorithms).  obj_out ([H][W] complex) and probe_out ([N][N]
+ * complex) are device buffers; results are there once the scan's stream
+ * reaches this point.  The scan's x, object, probe, iteration count and
+ * metrics are unchanged; x is materialised first, and the exit-wave buffer
+ * pty_get_state returns as y then holds P_D x_k. */
+pty_status pty_shadow(pty_scan *scan, float *obj_out, float *probe_out);
+
+/* One iteration of sequential projections (Introduction: the constraint sets
+ * visited one after another, in a fixed or shuffled order, with relaxed
+ * projections), for N <= 128 (PTY_ERR_UNSUPPORTED otherwise).  The sets are
+ * the per-position modulus sets; the step onto set j, with psi = P S_j O,
+ * psi' its Fourier-modulus projection and d = psi' - psi, is
+ *   O <- O + alpha S_j^T[conj(P) d] / max|P|^2
+ *   P <- P + beta conj(S_j O) d / max|S_j O|^2      (probe updated: blind and
+ *                                                     iteration >= probe_update_start)
+ * taken at the (O, P) of the start of the position's batch.  Batches: the
+ * positions of `order` (host array, a permutation of 0..J-1; NULL: ascending)
+ * are placed by dependency level into batches of pairwise disjoint windows,
+ * each overlapping pair keeping its order; max_batch > 0 caps a batch's size
+ * (1: strictly sequential).  A batch's object steps touch disjoint pixels; its
+ * probe steps are summed in batch order after it.  With a known probe every
+ * batch schedule equals the sequential order.  The Fourier error of the exit
+ * waves visited goes to the metric history (the other two metrics are NaN).
+ * The generalised iteration's exit waves are discarded: a following
+ * pty_iterate starts again from x = P S_j O. */
+pty_status pty_sp_iterate(pty_scan *scan, const int32_t *order, int32_t max_batch, double alpha, double beta);
+
+/* Number of batches of the last pty_sp_iterate call (-1 for NULL). */
+int32_t pty_sp_last_batches(const pty_scan *scan);
+
+/* Object error against a ground truth with the global complex scale removed
+ * (the object is determined only up to one complex factor in blind
+ * ptychography; the paper's error lines of Figs. 7-8 are measured inside a
+ * box of the object, Fig. 5): min over complex g of
+ *   sum |t - g O|^2 / sum |t|^2
+ * over the box rows [r0, r0+h), columns [c0, c0+w) of the scan's current
+ * object.  truth: device buffer, [h][w] complex, row-major.  Sums in
+ * float64 in a fixed order.  Synchronises the scan's stream; *err is NaN for
+ * an all-zero truth and 1 for an all-zero object. */
+pty_status pty_object_error(pty_scan *scan, const float *truth, int32_t r0, int32_t c0, int32_t h, int32_t w,
+                            double *err);
+
 /* Wait for all queued work of the scan. */
 pty_status pty_synchronize(pty_scan *scan);
 

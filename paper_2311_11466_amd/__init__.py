@@ -31,7 +31,8 @@ EXPORTS = [
     "pty_iterate", "pty_iterate_many", "pty_synchronize", "pty_get_object", "pty_get_probe",
     "pty_get_metrics", "pty_get_metric_history", "pty_get_iteration", "pty_get_state",
     "pty_set_state", "pty_destroy_scan", "pty_status_string", "pty_last_error",
-    "pty_profile", "pty_profile_read",
+    "pty_profile", "pty_profile_read", "pty_iterate_schedule", "pty_set_concur_sweeps", "pty_shadow",
+    "pty_object_error", "pty_sp_iterate", "pty_sp_last_batches",
 ]
 KERNEL_CLASSES = ["divide", "divide_cols", "divide_rows_inv", "object", "probe", "final"]
 
@@ -100,11 +101,21 @@ def load_library(path: str = LIB_PATH):
     L.pty_last_error.argtypes = []
     L.pty_last_error.restype = ctypes.c_char_p
     L.pty_profile.argtypes = [P, ctypes.c_int32]
+    L.pty_iterate_schedule.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
+    L.pty_set_concur_sweeps.argtypes = [P, ctypes.c_int32]
+    L.pty_shadow.argtypes = [P, P, P]
+    L.pty_object_error.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_double)]
+    L.pty_sp_iterate.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_double,
+                                 ctypes.c_double]
+    L.pty_sp_last_batches.argtypes = [P]
+    L.pty_sp_last_batches.restype = ctypes.c_int32
     L.pty_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                    ctypes.c_int32]
     for name in ("pty_profile", "pty_profile_read", "pty_create_scan", "pty_set_algorithm", "pty_set_algorithm_named", "pty_iterate",
                  "pty_iterate_many", "pty_synchronize", "pty_get_object", "pty_get_probe",
-                 "pty_get_metrics", "pty_get_metric_history", "pty_get_state", "pty_set_state"):
+                 "pty_get_metrics", "pty_get_metric_history", "pty_get_state", "pty_set_state",
+                 "pty_iterate_schedule", "pty_set_concur_sweeps", "pty_shadow", "pty_object_error", "pty_sp_iterate"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -201,6 +212,50 @@ class Scan:
 
     def iterate(self, n: int = 1):
         _check(self._L.pty_iterate(self._h, int(n)), "pty_iterate")
+
+    def iterate_schedule(self, abcs):
+        """One iteration per (a, b, c) triple of abcs, in order."""
+        flat = [float(v) for t in abcs for v in t]
+        if len(flat) % 3:
+            raise ValueError("abcs must hold (a, b, c) triples")
+        buf = (ctypes.c_double * max(1, len(flat)))(*flat)
+        _check(self._L.pty_iterate_schedule(self._h, buf, len(flat) // 3), "pty_iterate_schedule")
+
+    def set_concur_sweeps(self, sweeps: int):
+        _check(self._L.pty_set_concur_sweeps(self._h, int(sweeps)), "pty_set_concur_sweeps")
+
+    def shadow(self):
+        """The shadow estimate P_C(P_D x): (object, probe) as complex64 device tensors."""
+        o = self._empty(self.obj_h, self.obj_w)
+        p = self._empty(self.n, self.n)
+        _check(self._L.pty_shadow(self._h, ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(p.data_ptr())),
+               "pty_shadow")
+        self.synchronize()
+        return o, p
+
+    def sp_iterate(self, order=None, max_batch: int = 0, alpha: float = 1.0, beta: float = 1.0) -> int:
+        """One iteration of sequential projections; returns the number of batches."""
+        if order is None:
+            buf = None
+        else:
+            order = [int(v) for v in order]
+            if len(order) != self.n_pos:
+                raise ValueError(f"order must hold {self.n_pos} positions")
+            buf = (ctypes.c_int32 * len(order))(*order)
+        _check(self._L.pty_sp_iterate(self._h, buf, int(max_batch), float(alpha), float(beta)), "pty_sp_iterate")
+        return int(self._L.pty_sp_last_batches(self._h))
+
+    def object_error(self, truth_box, r0: int, c0: int) -> float:
+        """Aligned error of the current object against truth_box (a complex64
+        device tensor [h, w]) placed at (r0, c0)."""
+        torch = _torch()
+        t = truth_box.contiguous()
+        h, w = t.shape
+        torch.cuda.current_stream(self.device).synchronize()   # t may come from another stream
+        out = ctypes.c_double()
+        _check(self._L.pty_object_error(self._h, ctypes.c_void_p(t.data_ptr()), int(r0), int(c0), int(h), int(w),
+                                        ctypes.byref(out)), "pty_object_error")
+        return float(out.value)
 
     def synchronize(self):
         _check(self._L.pty_synchronize(self._h), "pty_synchronize")

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <exception>
@@ -30,6 +31,8 @@ constexpr size_t kAlign = 256;
 constexpr int kTileW = 64, kTileH = 16;
 constexpr int kDefaultCap = 4096;
 constexpr double kDefaultTau = 1e-10;
+constexpr int kMaxSweeps = 64;
+constexpr int kEvalBlocks = 64;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -43,7 +46,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 enum Mode { MODE_INIT = 0, MODE_MATERIAL = 1, MODE_PENDING = 2, MODE_PENDING_W = 3 };
 
 struct Layout {
-  size_t amp, x, y, tmp, obj, probe, pos, tile_off, tile_list, part, met, met2, ring, tile_max, pmax, tw, flag,
+  size_t amp, x, y, tmp, obj, probe, pos, tile_off, tile_list, part, met, met2, ring, tile_max, pmax, tw, flag, eval, sp_list,
       total;
   int tiles_x, tiles_y, n_tiles, max_list, G, chunk, npb, nslot, cap;
   size_t elem_bytes;
@@ -104,6 +107,8 @@ Layout make_layout(const pty_scan_desc* d) {
   L.pmax = take(size_t(L.npb) * 4);
   L.tw = take(N * 8);
   L.flag = take(64);
+  L.eval = take(size_t(kEvalBlocks + 1) * 4 * 8);   // object-error partial sums and result
+  L.sp_list = take(J * 4);                            // batch member lists of sequential projections
   L.total = off;
   return L;
 }
@@ -122,6 +127,10 @@ struct pty_scan {
   double a = 1.0, b = 1.0, c = 1.0;
   int64_t k = 0;
   int mode = MODE_INIT;
+  int sweeps = 1;                          // concur (object, probe) sweeps per iteration
+  std::vector<int> hpos;                   // positions (row, col) on the host
+  std::vector<int> sp_members;             // batch member lists of the last sequential-projection call
+  int sp_batches_last = 0;                 // batches of the last sequential-projection call
   float pa = 1.0f, pb = 0.0f, pg = 0.0f;  // pending prologue coefficients
   bool x_valid = false, y_valid = false;
   bool prev_metrics_done = true;          // metrics of iteration k-1 already finalised
@@ -230,6 +239,69 @@ FinalParams final_params(const pty_scan* s, const MetricParams& mp) {
 // One iteration: divide (with the pending update), object (+ metrics), [probe].
 pty_status flush(pty_scan* s, bool materialise);
 
+DivideParams divide_params(const pty_scan* s) {
+  DivideParams p{};
+  p.obj = s->at<float2>(s->L.obj);
+  p.probe = s->at<float2>(s->L.probe);
+  p.pos = s->at<int2>(s->L.pos);
+  p.amp = s->at<float>(s->L.amp);
+  p.tw = s->at<float2>(s->L.tw);
+  p.x = s->ws + s->L.x;
+  p.y = s->ws + s->L.y;
+  p.tmp = s->tmp_ptr();
+  p.obj_w = s->W;
+  p.j_begin = 0;
+  p.scale = s->scale;
+  p.inv_scale = s->inv_scale;
+  p.met = s->at<double>(s->L.met);
+  p.nslot = s->L.nslot;
+  return p;
+}
+
+// The concur of the y buffer into the scan's object and probe: s->sweeps
+// (object, probe) sweeps when the probe is updated, one object step
+// otherwise.  Every sweep's object launch writes the same metric slices and
+// every finalise the same ring entries (from mp), so repeating them is
+// harmless.
+pty_status launch_concur(pty_scan* s, const MetricParams& mp, bool update_probe, bool timed_launch) {
+  const hipStream_t st = s->stream;
+  ObjParams o{};
+  o.y = s->ws + s->L.y;
+  o.inv_scale = s->inv_scale;
+  o.probe = s->at<float2>(s->L.probe);
+  o.pos = s->at<int2>(s->L.pos);
+  o.tile_off = s->at<int>(s->L.tile_off);
+  o.tile_ent = s->at<int4>(s->L.tile_list);
+  o.obj = s->at<float2>(s->L.obj);
+  o.H = s->H; o.W = s->W; o.N = s->N;
+  o.tiles_x = s->L.tiles_x;
+  o.n_tiles = s->L.n_tiles;
+  o.tile_max = s->at<float>(s->L.tile_max);
+  o.pmax_part = s->at<float>(s->L.pmax);
+  o.npb = s->L.npb;
+  o.tau = s->tau;
+  o.mp = mp;
+  ProbeParams q{};
+  q.y = o.y;
+  q.inv_scale = s->inv_scale;
+  q.obj = o.obj;
+  q.pos = o.pos;
+  q.N = s->N; q.W = s->W; q.J = s->J;
+  q.chunk = s->L.chunk;
+  q.G = s->L.G;
+  q.part = s->at<double>(s->L.part);
+  const FinalParams f = final_params(s, mp);
+  const int n_sweeps = update_probe ? s->sweeps : 1;
+  auto run = [&](int cls, auto&& fn) { return timed_launch ? timed(s, cls, fn) : fn(); };
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    PTY_HIP(s, run(PTY_K_OBJECT, [&] { return launch_object_update(s->fp16, o, st); }), "object launch");
+    if (update_probe)
+      PTY_HIP(s, run(PTY_K_PROBE, [&] { return launch_probe_partial(s->fp16, q, st); }), "probe launch");
+    PTY_HIP(s, run(PTY_K_FINAL, [&] { return launch_probe_final(f, update_probe, st); }), "finalise launch");
+  }
+  return PTY_OK;
+}
+
 // Blend form (x buffer holds w, see MODE_PENDING_W): it saves the y read of
 // the next prologue when x and y are both needed, i.e. a != 1 and b != 1.
 // It leaves no x_k for the change metric, so it is used only without
@@ -246,17 +318,7 @@ pty_status launch_iteration(pty_scan* s) {
     const pty_status fs = flush(s, true);
     if (fs != PTY_OK) return fs;
   }
-  DivideParams p{};
-  p.obj = s->at<float2>(s->L.obj);
-  p.probe = s->at<float2>(s->L.probe);
-  p.pos = s->at<int2>(s->L.pos);
-  p.amp = s->at<float>(s->L.amp);
-  p.tw = s->at<float2>(s->L.tw);
-  p.x = s->ws + s->L.x;
-  p.y = s->ws + s->L.y;
-  p.tmp = s->tmp_ptr();
-  p.obj_w = s->W;
-  p.j_begin = 0;
+  DivideParams p = divide_params(s);
   float al = 1.f, be = 0.f, ga = 0.f;
   if (s->mode == MODE_MATERIAL) { al = 0.f; be = 0.f; ga = 1.f; }
   if (s->mode == MODE_PENDING) { al = s->pa; be = s->pb; ga = s->pg; }
@@ -283,10 +345,6 @@ pty_status launch_iteration(pty_scan* s) {
   }
   p.write_x = write_x;
   p.c = float(s->c);
-  p.scale = s->scale;
-  p.inv_scale = s->inv_scale;
-  p.met = s->at<double>(s->L.met);
-  p.nslot = s->L.nslot;
   if (s->prof && s->ev_class.size() > 4096) PTY_HIP(s, drain_profile(s), "profile drain");
   for (int stage = 0; stage < divide_stages(s->N); ++stage) {
     PTY_HIP(s, timed(s, PTY_K_DIVIDE + stage,
@@ -294,43 +352,14 @@ pty_status launch_iteration(pty_scan* s) {
             "divide launch");
   }
 
-  ObjParams o{};
-  o.y = s->ws + s->L.y;
-  o.inv_scale = s->inv_scale;
-  o.probe = p.probe;
-  o.pos = p.pos;
-  o.tile_off = s->at<int>(s->L.tile_off);
-  o.tile_ent = s->at<int4>(s->L.tile_list);
-  o.obj = s->at<float2>(s->L.obj);
-  o.H = s->H; o.W = s->W; o.N = s->N;
-  o.tiles_x = s->L.tiles_x;
-  o.n_tiles = s->L.n_tiles;
-  o.tile_max = s->at<float>(s->L.tile_max);
-  o.pmax_part = s->at<float>(s->L.pmax);
-  o.npb = s->L.npb;
-  o.tau = s->tau;
-  o.mp = metric_params(s, object_blocks(s->N, s->L.n_tiles));
-  o.mp.k_cur = s->k;
-  o.mp.k_prev = (p.prev_ec || p.prev_dx) ? s->k - 1 : -1;
-  o.mp.ec_ok = p.prev_ec;
-  o.mp.dx_ok = p.prev_dx;
-  PTY_HIP(s, timed(s, PTY_K_OBJECT, [&] { return launch_object_update(s->fp16, o, st); }), "object launch");
-
   const bool update_probe = s->blind && s->k >= s->probe_update_start;
-  if (update_probe) {
-    ProbeParams q{};
-    q.y = o.y;
-    q.inv_scale = s->inv_scale;
-    q.obj = o.obj;
-    q.pos = p.pos;
-    q.N = s->N; q.W = s->W; q.J = s->J;
-    q.chunk = s->L.chunk;
-    q.G = s->L.G;
-    q.part = s->at<double>(s->L.part);
-    PTY_HIP(s, timed(s, PTY_K_PROBE, [&] { return launch_probe_partial(s->fp16, q, st); }), "probe launch");
-  }
-  const FinalParams f = final_params(s, o.mp);
-  PTY_HIP(s, timed(s, PTY_K_FINAL, [&] { return launch_probe_final(f, update_probe, st); }), "finalise launch");
+  MetricParams mp = metric_params(s, object_blocks(s->N, s->L.n_tiles));
+  mp.k_cur = s->k;
+  mp.k_prev = (p.prev_ec || p.prev_dx) ? s->k - 1 : -1;
+  mp.ec_ok = p.prev_ec;
+  mp.dx_ok = p.prev_dx;
+  const pty_status cs = launch_concur(s, mp, update_probe, true);
+  if (cs != PTY_OK) return cs;
 
   // the new state is pending with this iteration's (a, b)
   s->mode = wf ? MODE_PENDING_W : MODE_PENDING;
@@ -519,6 +548,7 @@ pty_status create_impl(const pty_scan_desc* d, void* d_ws, size_t ws_bytes, void
   s->stream = st;
   s->ws = reinterpret_cast<char*>(d_ws);
   s->L = L;
+  s->hpos = pos;
   if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
 
   auto bail = [&](pty_status r) { delete s; return r; };
@@ -667,6 +697,197 @@ pty_status pty_iterate_many(pty_scan* const* scans, int32_t count, int32_t n) {
   } catch (...) {
     return fail(PTY_ERR_DEVICE, "exception during iterate_many");
   }
+  return PTY_OK;
+}
+
+pty_status pty_iterate_schedule(pty_scan* scan, const double* abc, int32_t n) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (n < 0 || (n > 0 && !abc)) return fail(PTY_ERR_INVALID_ARG, "bad abc/n");
+  for (int32_t i = 0; i < n; ++i) {
+    if (!finite_abc(abc[3 * i], abc[3 * i + 1], abc[3 * i + 2]))
+      return fail(PTY_ERR_INVALID_ARG, "schedule entry " + std::to_string(i) + ": a, b, c must be finite");
+    if (abc[3 * i] == 0.0) return fail(PTY_ERR_INVALID_ARG, "schedule entry " + std::to_string(i) + ": a is zero");
+  }
+  try {
+    for (int32_t i = 0; i < n; ++i) {
+      scan->a = abc[3 * i];
+      scan->b = abc[3 * i + 1];
+      scan->c = abc[3 * i + 2];
+      st = launch_iteration(scan);
+      if (st != PTY_OK) return st;
+    }
+  } catch (...) {
+    scan->failed = true;
+    return fail(PTY_ERR_DEVICE, "exception during iterate_schedule");
+  }
+  return PTY_OK;
+}
+
+pty_status pty_set_concur_sweeps(pty_scan* scan, int32_t sweeps) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (sweeps < 1 || sweeps > kMaxSweeps) return fail(PTY_ERR_INVALID_ARG, "sweeps must be in [1, 64]");
+  scan->sweeps = sweeps;
+  return PTY_OK;
+}
+
+pty_status pty_shadow(pty_scan* scan, float* obj_out, float* probe_out) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (!obj_out || !probe_out) return fail(PTY_ERR_INVALID_ARG, "obj_out and probe_out must be device buffers");
+  try {
+    st = flush(scan, true);                    // x_k materialised
+    if (st != PTY_OK) return st;
+    const hipStream_t s = scan->stream;
+    // unrelaxed divide of x_k into the y buffer (x is rewritten unchanged)
+    DivideParams p = divide_params(scan);
+    p.alpha = 0.f; p.beta = 0.f; p.gamma = 1.f;
+    p.read_x = 1; p.read_y = 0; p.write_x = 1;
+    p.c = 1.0f;
+    for (int stage = 0; stage < divide_stages(scan->N); ++stage)
+      PTY_HIP(scan, launch_divide_stage(scan->N, scan->fp16, p, scan->J, stage, s), "shadow divide");
+    scan->y_valid = false;
+    // the consensus runs in place; the outputs first receive the current
+    // (O, P) and are swapped with the result afterwards
+    float2* O = scan->at<float2>(scan->L.obj);
+    float2* P = scan->at<float2>(scan->L.probe);
+    const size_t no = size_t(scan->H) * scan->W, np = size_t(scan->N) * scan->N;
+    PTY_HIP(scan, hipMemcpyAsync(obj_out, O, no * 8, hipMemcpyDeviceToDevice, s), "shadow copy");
+    PTY_HIP(scan, hipMemcpyAsync(probe_out, P, np * 8, hipMemcpyDeviceToDevice, s), "shadow copy");
+    MetricParams mp = metric_params(scan, object_blocks(scan->N, scan->L.n_tiles));   // writes no ring entry
+    st = launch_concur(scan, mp, scan->blind && scan->k >= scan->probe_update_start, false);
+    if (st != PTY_OK) return st;
+    PTY_HIP(scan, launch_swap(O, reinterpret_cast<float2*>(obj_out), no, s), "shadow swap");
+    PTY_HIP(scan, launch_swap(P, reinterpret_cast<float2*>(probe_out), np, s), "shadow swap");
+    st = refresh_probe_max(scan);
+    if (st != PTY_OK) return st;
+  } catch (...) {
+    scan->failed = true;
+    return fail(PTY_ERR_DEVICE, "exception during shadow");
+  }
+  return PTY_OK;
+}
+
+// Batches of pairwise disjoint windows by dependency level: position j goes
+// to the batch after the last one holding an overlapping position placed
+// before it (further on while batches are full), so every overlapping pair
+// keeps the order.
+static std::vector<std::vector<int>> sp_batches(const std::vector<int>& pos, const std::vector<int>& order, int n,
+                                                int max_batch) {
+  std::vector<std::vector<int>> batches;
+  std::vector<int> where(order.size(), -1);
+  std::vector<int> placed;
+  placed.reserve(order.size());
+  for (int j : order) {
+    int last = -1;
+    for (int i : placed) {
+      if (where[i] > last && std::abs(pos[2 * i] - pos[2 * j]) < n && std::abs(pos[2 * i + 1] - pos[2 * j + 1]) < n)
+        last = where[i];
+    }
+    int b = last + 1;
+    while (max_batch > 0 && b < int(batches.size()) && int(batches[b].size()) >= max_batch) ++b;
+    if (b == int(batches.size())) batches.emplace_back();
+    batches[b].push_back(j);
+    where[j] = b;
+    placed.push_back(j);
+  }
+  return batches;
+}
+
+pty_status pty_sp_iterate(pty_scan* scan, const int32_t* order, int32_t max_batch, double alpha, double beta) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (scan->N > 128) return fail(PTY_ERR_UNSUPPORTED, "sequential projections are built for N <= 128");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(PTY_ERR_INVALID_ARG, "alpha, beta must be finite");
+  if (max_batch < 0) return fail(PTY_ERR_INVALID_ARG, "max_batch must be >= 0");
+  const int J = scan->J, N = scan->N;
+  // the probe steps of a batch (up to J of N^2 complex float32) live in the
+  // exit-wave buffers x and y, which are adjacent
+  if (size_t(J) * N * N * 8 > scan->L.y + size_t(J) * N * N * scan->L.elem_bytes - scan->L.x)
+    return fail(PTY_ERR_DEVICE, "internal: exit-wave buffers too small for the probe steps");
+  std::vector<int> ord(J);
+  if (order) {
+    std::vector<char> seen(J, 0);
+    for (int i = 0; i < J; ++i) {
+      const int j = order[i];
+      if (j < 0 || j >= J || seen[j]) return fail(PTY_ERR_INVALID_ARG, "order must be a permutation of 0..J-1");
+      seen[j] = 1;
+      ord[i] = j;
+    }
+  } else {
+    for (int i = 0; i < J; ++i) ord[i] = i;
+  }
+  try {
+    st = flush(scan, false);                  // metrics of the previous iteration, if pending
+    if (st != PTY_OK) return st;
+    const auto batches = sp_batches(scan->hpos, ord, N, max_batch);
+    scan->sp_members.clear();
+    for (const auto& b : batches) scan->sp_members.insert(scan->sp_members.end(), b.begin(), b.end());
+    const hipStream_t s = scan->stream;
+    int* d_list = scan->at<int>(scan->L.sp_list);
+    PTY_HIP(scan, hipMemcpyAsync(d_list, scan->sp_members.data(), size_t(J) * 4, hipMemcpyHostToDevice, s),
+            "batch lists");
+    const bool blind = scan->blind && scan->k >= scan->probe_update_start;
+    DivideParams p = divide_params(scan);
+    p.alpha = 1.f;                            // psi = P S_j O
+    p.c = 1.0f;
+    p.obj_out = scan->at<float2>(scan->L.obj);
+    p.contrib = scan->at<float2>(scan->L.x);  // x and y hold no state during sequential projections
+    p.pmax_part = scan->at<float>(scan->L.pmax);
+    p.npb = scan->L.npb;
+    p.sp_alpha = float(alpha);
+    p.sp_beta = float(beta);
+    p.sp_blind = blind;
+    SpProbeParams q{};
+    q.probe = scan->at<float2>(scan->L.probe);
+    q.contrib = p.contrib;
+    q.N = N;
+    q.pmax_part = scan->at<float>(scan->L.pmax);
+    int off = 0;
+    for (const auto& b : batches) {
+      p.batch = d_list + off;
+      PTY_HIP(scan, timed(scan, PTY_K_DIVIDE, [&] { return launch_sp_batch(N, p, int(b.size()), s); }),
+              "sequential projection launch");
+      if (blind) {
+        q.count = int(b.size());
+        PTY_HIP(scan, timed(scan, PTY_K_PROBE, [&] { return launch_sp_probe(q, s); }), "probe step launch");
+      }
+      off += int(b.size());
+    }
+    MetricParams m = metric_params(scan, 1);
+    m.k_cur = scan->k;
+    PTY_HIP(scan, launch_metric_slices(m, s), "metrics launch");
+    PTY_HIP(scan, launch_probe_final(final_params(scan, m), 0, s), "metrics launch");
+    scan->sp_batches_last = int(batches.size());
+    scan->k += 1;
+    scan->mode = MODE_INIT;                   // the next generalised iteration starts from x = P S_j O
+    scan->x_valid = scan->y_valid = false;
+    scan->prev_metrics_done = true;
+  } catch (...) {
+    scan->failed = true;
+    return fail(PTY_ERR_DEVICE, "exception during sequential projections");
+  }
+  return PTY_OK;
+}
+
+int32_t pty_sp_last_batches(const pty_scan* scan) { return scan ? scan->sp_batches_last : -1; }
+
+pty_status pty_object_error(pty_scan* scan, const float* truth, int32_t r0, int32_t c0, int32_t h, int32_t w,
+                            double* err) {
+  pty_status st = check_usable(scan);
+  if (st != PTY_OK) return st;
+  if (!truth || !err) return fail(PTY_ERR_INVALID_ARG, "truth and err must be given");
+  if (h < 1 || w < 1 || r0 < 0 || c0 < 0 || r0 + h > scan->H || c0 + w > scan->W)
+    return fail(PTY_ERR_INVALID_ARG, "the box must lie inside the object");
+  double* part = scan->at<double>(scan->L.eval);
+  PTY_HIP(scan, launch_object_error(scan->at<float2>(scan->L.obj), scan->W, reinterpret_cast<const float2*>(truth),
+                                    r0, c0, h, w, part, kEvalBlocks, scan->stream),
+          "object error");
+  double out = 0.0;
+  PTY_HIP(scan, hipMemcpyAsync(&out, part + 4 * kEvalBlocks, 8, hipMemcpyDeviceToHost, scan->stream), "copy");
+  PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
+  *err = out;
   return PTY_OK;
 }
 

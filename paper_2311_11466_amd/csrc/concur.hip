@@ -15,6 +15,8 @@
 // pixels a chunk or tile row gathers stay in one L2.  The object launch also
 // sums slices of the metric partials, which the finalise kernel's last block
 // adds up.
+#include <algorithm>
+
 #include "common.hpp"
 #include "params.hpp"
 
@@ -444,6 +446,67 @@ hipError_t launch_probe_final(const FinalParams& p, int update_probe, hipStream_
   q.first_block = update_probe ? 0 : p.npb;
   const int blocks = update_probe ? p.npb + 1 : 1;
   hipLaunchKernelGGL(probe_final_kernel, dim3(blocks), dim3(256), 0, s, q);
+  return hipGetLastError();
+}
+
+// Exchange two complex arrays element by element (no temporary buffer).
+__global__ void swap_kernel(float2* __restrict__ a, float2* __restrict__ b, size_t count) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < count; i += size_t(gridDim.x) * blockDim.x) {
+    const float2 t = a[i];
+    a[i] = b[i];
+    b[i] = t;
+  }
+}
+
+hipError_t launch_swap(float2* a, float2* b, size_t count, hipStream_t s) {
+  const int blocks = int(std::min<size_t>((count + 255) / 256, 8192));
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(swap_kernel, dim3(blocks), dim3(256), 0, s, a, b, count);
+  return hipGetLastError();
+}
+
+// Object error against ground truth with the global complex scale removed:
+// with S_tt = sum |t|^2, S_oo = sum |o|^2, S_ot = sum conj(o) t over the box,
+// min_g sum |t - g o|^2 = S_tt - |S_ot|^2 / S_oo (g = S_ot / S_oo).  Rows are
+// split over the blocks in order; float64 sums in a fixed order.
+__global__ __launch_bounds__(256) void object_error_part_kernel(const float2* __restrict__ o, int ow,
+                                                                const float2* __restrict__ t, int r0, int c0,
+                                                                int h, int w, double* part) {
+  __shared__ double red[4 * 4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const size_t total = size_t(h) * w;
+  const size_t per = (total + gridDim.x - 1) / gridDim.x;
+  const size_t i0 = blockIdx.x * per, i1 = min(total, i0 + per);
+  for (size_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    const int r = int(i / w), c = int(i % w);
+    const float2 a = o[size_t(r0 + r) * ow + (c0 + c)];
+    const float2 b = t[i];
+    const double ox = a.x, oy = a.y, tx = b.x, ty = b.y;
+    acc[0] += tx * tx + ty * ty;
+    acc[1] += ox * ox + oy * oy;
+    acc[2] += ox * tx + oy * ty;     // Re conj(o) t
+    acc[3] += ox * ty - oy * tx;     // Im conj(o) t
+  }
+  block_sum<4, 256>(acc, red);
+  if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = acc[threadIdx.x];
+}
+
+__global__ void object_error_finish_kernel(double* part, int blocks) {
+  if (threadIdx.x != 0) return;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < blocks; ++b)
+    for (int q = 0; q < 4; ++q) s[q] += part[b * 4 + q];
+  double e = __builtin_nan("");
+  if (s[0] > 0.0) e = s[1] > 0.0 ? (s[0] - (s[2] * s[2] + s[3] * s[3]) / s[1]) / s[0] : 1.0;
+  part[blocks * 4] = e;
+}
+
+hipError_t launch_object_error(const float2* o, int ow, const float2* t, int r0, int c0, int h, int w, double* part,
+                               int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(object_error_part_kernel, dim3(blocks), dim3(256), 0, s, o, ow, t, r0, c0, h, w, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(object_error_finish_kernel, dim3(1), dim3(64), 0, s, part, blocks);
   return hipGetLastError();
 }
 

@@ -77,15 +77,16 @@ __device__ __forceinline__ float2 fourier_op(float2 X, float A, float c, float o
 // (w = 0: the first iteration, or a blend with beta' = gamma' = 0).
 enum ProMode {
   PRO_GENERAL = 0, PRO_UPDATE = 1, PRO_MATERIAL = 2, PRO_INIT = 3, PRO_FLAGS = 4,
-  PRO_W_PENDING = 5, PRO_W_MATERIAL = 6, PRO_W_ZERO = 7
+  PRO_W_PENDING = 5, PRO_W_MATERIAL = 6, PRO_W_ZERO = 7, PRO_SP = 8
 };
 
 template <int MODE>
 struct Pro {
+  static constexpr bool sp = MODE == PRO_SP;          // sequential projections (psi kept like x_k)
   static constexpr bool wf = MODE >= PRO_W_PENDING;
   static constexpr bool gather = MODE != PRO_W_MATERIAL;
   static constexpr bool rx(const DivideParams& p) {
-    return MODE == PRO_FLAGS ? p.read_x : (MODE != PRO_INIT && MODE != PRO_W_ZERO);
+    return MODE == PRO_FLAGS ? p.read_x : (MODE != PRO_INIT && MODE != PRO_W_ZERO && MODE != PRO_SP);
   }
   static constexpr bool ry(const DivideParams& p) {
     return MODE == PRO_FLAGS ? p.read_y : (MODE == PRO_GENERAL || MODE == PRO_UPDATE);
@@ -137,7 +138,7 @@ void divide_fused_kernel(DivideParams p) {
   __shared__ double red[MF_COUNT * (T / 64)];
 
   const unsigned tid = threadIdx.x;
-  const int j = p.j_begin + blockIdx.x;
+  const int j = PR::sp ? p.batch[blockIdx.x] : p.j_begin + int(blockIdx.x);
   const size_t base = size_t(j) * (N * N);
   const int2 pj = p.pos[j];
   using elem = typename St::elem;
@@ -153,6 +154,9 @@ void divide_fused_kernel(DivideParams p) {
 
   float2 v[E];
   float2 xk[PR::wf ? E : 1];   // blend form: x_k, kept for w_k (registers are not the limit: LDS is)
+  float om = 0.0f;             // sequential projections: max |S_j O|^2 over the window
+  float sp_ka = 0.f, sp_kb = 0.f;
+  float2* ob_out = nullptr;   // the same window as ob (sequential projections write it)
   float ec_n = 0.f, ec_d = 0.f, dx_n = 0.f, dx_d = 0.f, ef_n = 0.f, ef_d = 0.f;
 
   // ---- prologue and stage A, set by set -----------------------------------
@@ -181,6 +185,7 @@ void divide_fused_kernel(DivideParams p) {
         const float2 z = PR::gather ? cmul(zp[q.value], zo[q.value]) : make_float2(0.f, 0.f);
         const float2 xn = PR::wf ? blend_x(z, xo[q.value], p.alpha)
                                  : update_x(z, yo[q.value], xo[q.value], p.alpha, p.beta, p.gamma);
+        if constexpr (PR::sp) om = fmaxf(om, cnorm(zo[q.value]));
         if (mec) {
           const float dr = z.x - yo[q.value].x, di = z.y - yo[q.value].y;
           ec_n = fmaf(dr, dr, fmaf(di, di, ec_n));
@@ -298,7 +303,32 @@ void divide_fused_kernel(DivideParams p) {
       v[s.value * 16 + e.value] = t;
     });
     dft4x4_reg<true, s.value * 16>(v);
-    if (PR::wf && wx_blend) {
+    if constexpr (PR::sp) {
+      // d = psi' - psi; object step into the window, probe step to this slot
+      static_for<0, 16, G::GP>([&](auto g0) {
+        float2 pp[G::GP], oo[G::GP];
+        static_for<0, G::GP>([&](auto q) {
+          constexpr int e = g0.value + q.value;
+          constexpr int r1 = e / 4, c1 = e % 4;
+          const unsigned r = r2 + M * r1, c = c2 + M * c1;
+          pp[q.value] = pb[r * N + c];
+          oo[q.value] = ob_out[r * ow + c];
+        });
+        static_for<0, G::GP>([&](auto q) {
+          constexpr int e = g0.value + q.value;
+          constexpr int r1 = e / 4, c1 = e % 4;
+          const unsigned r = r2 + M * r1, c = c2 + M * c1;
+          const float2 d = csub(v[s.value * 16 + e], xk[s.value * 16 + e]);
+          const float2 po = cmulc(d, pp[q.value]);       // conj(P) d
+          ob_out[r * ow + c] = make_float2(fmaf(sp_ka, po.x, oo[q.value].x), fmaf(sp_ka, po.y, oo[q.value].y));
+          if (p.sp_blind) {
+            const float2 oc = cmulc(d, oo[q.value]);     // conj(S_j O) d
+            p.contrib[size_t(blockIdx.x) * (N * N) + r * N + c] = make_float2(sp_kb * oc.x, sp_kb * oc.y);
+          }
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    } else if (PR::wf && wx_blend) {
       // blend form: w_k from the x_k kept in registers since the prologue
       static_for<0, 16>([&](auto e) {
         constexpr int r1 = e.value / 4, c1 = e.value % 4;
@@ -327,6 +357,16 @@ void divide_fused_kernel(DivideParams p) {
     const unsigned r2 = qa / M, c2 = qa % M;
     static_for<0, 16>([&](auto kk) { v[s.value * 16 + kk.value] = lds[r2 * PA + c2 * 17 + kk.value]; });
   });
+  if constexpr (PR::sp) {
+    // step sizes alpha / max|P|^2 and beta / max|S_j O|^2 (zero when the maximum is zero)
+    __shared__ float fred[T / 64];
+    float pm = 0.f;
+    for (int i = 0; i < p.npb; ++i) pm = fmaxf(pm, p.pmax_part[i]);
+    const float omx = block_max<T>(om, fred);
+    sp_ka = pm > 0.f ? p.sp_alpha / pm : 0.f;
+    sp_kb = omx > 0.f ? p.sp_beta / omx : 0.f;
+    ob_out = p.obj_out + (size_t(pj.x) * p.obj_w + pj.y);
+  }
   static_for<0, SA>([&](auto s) { finish_set(s); });
 
   // ---- per-pattern metric partials (float64 block sums) ----------------------
@@ -548,6 +588,43 @@ static hipError_t launch_divide_t(int n, const DivideParams& p, int n_patterns, 
     case 256: return launch_256<St>(p, n_patterns, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_sp_batch(int n, const DivideParams& p, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  switch (n) {
+    case 32: launch_fused_mode<32, 64, StoreF32, PRO_SP>(p, count, s); break;
+    case 64: launch_fused_mode<64, 256, StoreF32, PRO_SP>(p, count, s); break;
+    case 128: launch_fused_mode<128, 512, StoreF32, PRO_SP>(p, count, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void sp_probe_kernel(SpProbeParams p) {
+  __shared__ float red[4];
+  const int NN = p.N * p.N;
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  float m = 0.f;
+  if (u < NN) {
+    double ax = 0.0, ay = 0.0;
+    for (int k = 0; k < p.count; ++k) {
+      const float2 c = p.contrib[size_t(k) * NN + u];
+      ax += c.x;
+      ay += c.y;
+    }
+    const float2 o = p.probe[u];
+    const float2 nv = make_float2(float(double(o.x) + ax), float(double(o.y) + ay));
+    p.probe[u] = nv;
+    m = cnorm(nv);
+  }
+  m = block_max<256>(m, red);
+  if (threadIdx.x == 0) p.pmax_part[blockIdx.x] = m;
+}
+
+hipError_t launch_sp_probe(const SpProbeParams& p, hipStream_t s) {
+  hipLaunchKernelGGL(sp_probe_kernel, dim3((p.N * p.N + 255) / 256), dim3(256), 0, s, p);
+  return hipGetLastError();
 }
 
 hipError_t launch_divide(int n, int fp16, const DivideParams& p, int n_patterns, hipStream_t s) {

@@ -39,6 +39,27 @@ struct DivideParams {
   // stores w_k = next_gamma * x_k + next_beta * y_k (if write_x) beside y_k.
   int wform;
   float next_beta, next_gamma;
+  // Sequential projections (one launch per batch of disjoint windows): the
+  // work-group of slot s handles pattern batch[s]; the prologue forms
+  // psi = P S_j O, the Fourier step is the unrelaxed modulus projection, the
+  // epilogue adds sp_alpha conj(P) d / max|P|^2 to the object window and
+  // writes sp_beta conj(S_j O) d / max|S_j O|^2 to contrib[s] (d = psi' - psi).
+  const int* batch;
+  float2* obj_out;          // the object, written in place (windows of a batch are disjoint)
+  float2* contrib;          // [batch size][N][N] probe steps (blind)
+  const float* pmax_part;   // [npb] partial maxima of |P|^2
+  int npb;
+  float sp_alpha, sp_beta;
+  int sp_blind;
+};
+
+// Probe update after a batch of sequential projections: P += sum over the
+// batch's slots (in order) of contrib, float64 sums; then the partial maxima.
+struct SpProbeParams {
+  float2* probe;
+  const float2* contrib;
+  int count, N;
+  float* pmax_part;
 };
 
 // Metric finalisation of one iteration: a fixed-order two-level float64
@@ -127,6 +148,14 @@ hipError_t launch_probe_partial(int fp16, const ProbeParams& p, hipStream_t s);
 hipError_t launch_flush(int fp16, const FlushParams& p, int J, hipStream_t s);
 hipError_t launch_probe_final(const FinalParams& p, int update_probe, hipStream_t s);
 hipError_t launch_metric_slices(const MetricParams& p, hipStream_t s);
+hipError_t launch_swap(float2* a, float2* b, size_t count, hipStream_t s);
+hipError_t launch_sp_batch(int n, const DivideParams& p, int count, hipStream_t s);
+hipError_t launch_sp_probe(const SpProbeParams& p, hipStream_t s);
+// min over complex g of sum |t - g o|^2 / sum |t|^2 over the box [r0, r0+h) x [c0, c0+w)
+// of o (row pitch ow) against t ([h][w]); part holds 4 (blocks + 1) doubles, the
+// result lands in part[4 blocks]
+hipError_t launch_object_error(const float2* o, int ow, const float2* t, int r0, int c0, int h, int w, double* part,
+                               int blocks, hipStream_t s);
 hipError_t launch_amp_prepare(int n, const float* intensity, float* amp, int J, int* bad, hipStream_t s);
 hipError_t launch_max_abs2_parts(const float2* a, size_t count, float* parts, int nparts, hipStream_t s);
 hipError_t launch_convert_state(int fp16, int to_store, const float2* src, void* dst_store,

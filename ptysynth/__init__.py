@@ -15,6 +15,7 @@ from .scans import (  # noqa: F401
     CONFIGS,
     make_scan,
     make_request,
+    comparison_config,
     smooth_object,
     disc_probe,
     raster_positions,

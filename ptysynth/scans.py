@@ -217,6 +217,20 @@ def small_config(name: str, n: int, raster: int, step: int, jitter: int = 1,
                       photons, seed, seed + 1, seed + 2 if photons else None, 0.8 * r, n_pos)
 
 
+def comparison_config(probe: str, photons: Optional[float] = 1e6) -> ScanConfig:
+    """The algorithm comparison of the paper's Figs. 7-8: one synthetic object
+    and raster, measured with a big or a small probe (the two probes of
+    Fig. 6).  N = 64, a 16 x 16 raster of pitch 12; probe radius 24 (linear
+    overlap 75 %) or 12 (50 %); Poisson data at `photons` per pattern."""
+    if probe not in ("big", "small"):
+        raise ValueError("probe must be 'big' or 'small'")
+    n, raster, step, jitter, margin = 64, 16, 12, 1, 4
+    span = (raster - 1) * step + n + 2 * jitter + 2 * margin
+    r = 24.0 if probe == "big" else 12.0
+    return ScanConfig(f"compare_{probe}", span, span, n, (raster, raster), step, jitter, r, 0.5 * math.pi,
+                      photons, 601, 602, 603 if photons else None, 0.8 * r)
+
+
 def make_request(i: int, base_seed: int = 501000):
     """One request of the served mixed load: (ScanConfig, algorithm name, parameter).
 

@@ -72,6 +72,11 @@ def test_null_arguments(lib):
     assert lib.pty_iterate(None, 1) == 1
     assert lib.pty_set_algorithm(None, 1.0, 1.0, 1.0) == 1
     assert lib.pty_get_iteration(None) == -1
+    assert lib.pty_iterate_schedule(None, None, 1) == 1
+    assert lib.pty_set_concur_sweeps(None, 2) == 1
+    assert lib.pty_shadow(None, None, None) == 1
+    assert lib.pty_sp_iterate(None, None, 0, 1.0, 1.0) == 1
+    assert lib.pty_sp_last_batches(None) == -1
     lib.pty_destroy_scan(None)  # no-op
 
 
