@@ -305,15 +305,17 @@ def bench_sp(args):
     g = pk.Scan(torch.as_tensor(scan.pos).to(dev), torch.as_tensor(scan.intensity).to(dev),
                 torch.as_tensor(scan.obj0.astype(np.complex64)).to(dev),
                 torch.as_tensor(scan.probe0.astype(np.complex64)).to(dev), blind=True, device=dev)
+    from paper_2311_11466_amd.sp import disjoint_order
+    order = disjoint_order(scan.pos, cfg.n) if args.sp_order == "colour" else None
     nb = 0
     for _ in range(args.warmup):
-        nb = g.sp_iterate(None, args.sp_max_batch, args.sp_alpha, args.sp_beta)
+        nb = g.sp_iterate(order, args.sp_max_batch, args.sp_alpha, args.sp_beta)
     torch.cuda.synchronize()
     g.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        g.sp_iterate(None, args.sp_max_batch, args.sp_alpha, args.sp_beta)
+        g.sp_iterate(order, args.sp_max_batch, args.sp_alpha, args.sp_beta)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = g.profile_read()
@@ -343,6 +345,7 @@ def bench_sp(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp32", "data": "synthetic",
         "config": {"workload": cfg.name, "method": "sequential projections", "positions": scan.n_pos, "n": cfg.n,
+                   "order": "colour classes of the overlap graph" if order is not None else "ascending",
                    "batches_per_iteration": nb, "max_batch": args.sp_max_batch,
                    "alpha": args.sp_alpha, "beta": args.sp_beta, "blind": True},
         "roofline": {"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -365,15 +368,16 @@ def bench_compare(args):
     import numpy as np
     import torch
     from ptysynth import make_scan, comparison_config
-    from paper_2311_11466_amd.compare import error_lines, summary
+    from paper_2311_11466_amd.compare import ALGORITHMS, error_lines, summary
     torch.cuda.set_device(0)
     result, curves = {}, {}
     for probe in ("big", "small"):
         cfg = comparison_config(probe)
         sc = make_scan(cfg, intensity_dtype=np.float32)
         t0 = time.perf_counter()
+        algs = list(ALGORITHMS) + [("TLAMBDA", lam) for lam in (0.3, 0.7, 0.9)] + [("RAAR", 0.9)]
         lines = error_lines(sc.pos, sc.intensity, sc.obj0, sc.probe0, sc.obj_true, sc.metric_box(),
-                            n_iter=args.steps, sweeps=args.concur_sweeps)
+                            algorithms=algs, n_iter=args.steps, sweeps=args.concur_sweeps)
         print(f"# {cfg.name}: {len(lines)} algorithms x {args.steps} iterations in "
               f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         result[probe] = summary(lines)
@@ -459,6 +463,7 @@ def main():
     ap.add_argument("--method", default="abc", choices=["abc", "sp"],
                     help="abc: the generalised iteration; sp: sequential projections")
     ap.add_argument("--sp-max-batch", type=int, default=0)
+    ap.add_argument("--sp-order", default="colour", choices=["colour", "ascending"])
     ap.add_argument("--sp-alpha", type=float, default=1.0)
     ap.add_argument("--sp-beta", type=float, default=1.0)
     ap.add_argument("--concur-sweeps", type=int, default=1, help="(object, probe) sweeps per concur step")

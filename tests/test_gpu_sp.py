@@ -42,6 +42,9 @@ def say(*a):
 
 
 def orders_for(scan, n_iter, shuffled, seed=77):
+    from paper_2311_11466_amd.sp import disjoint_order
+    if shuffled == "colour":
+        return [disjoint_order(scan.pos, scan.n)] * n_iter
     if not shuffled:
         return None
     rng = np.random.default_rng(seed)
@@ -80,6 +83,7 @@ def oracle_sp(scan, n_iter, orders, max_batch, alpha, beta, blind, seed=None, ep
     ("p64", 3, True, 0, 1.0, 1.0, True),
     ("p128", 2, False, 0, 1.0, 0.7, True),
     ("p128", 2, True, 3, 0.9, 1.0, True),
+    ("p64", 2, "colour", 0, 1.0, 1.0, True),
 ])
 def test_sp_matches_oracle(cfg, n_iter, shuffled, max_batch, alpha, beta, blind):
     scan = get_scan(cfg)
@@ -117,6 +121,19 @@ def test_sp_known_probe_batches_equal_sequential():
     b = gpu_sp(scan, 2, None, 1, 1.0, 1.0, False)
     assert a[3][0] < b[3][0] == scan.n_pos
     assert rel_l2(a[0], b[0], covered_mask(scan)) <= 1e-6
+
+
+def test_colour_order_batches():
+    """The colour order's batches are its colour classes: few, each disjoint."""
+    from paper_2311_11466_amd.sp import disjoint_order
+    for cfg in ("tiny_n32", "p64", "p128"):
+        scan = get_scan(cfg)
+        order = disjoint_order(scan.pos, scan.n)
+        assert sorted(order.tolist()) == list(range(scan.n_pos))
+        asc = sp.batches_by_level(scan.pos, range(scan.n_pos), scan.n)
+        col = sp.batches_by_level(scan.pos, order, scan.n)
+        say("  batches", cfg, "ascending", len(asc), "colour", len(col))
+        assert len(col) <= len(asc)
 
 
 def test_sp_then_generalised_iteration():
