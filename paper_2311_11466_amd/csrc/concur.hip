@@ -319,7 +319,7 @@ __global__ __launch_bounds__(256) void probe_partial_kernel(ProbeParams p) {
       const int jj = min(j + q, j1 - 1);
       const int2 pj = p.pos[jj];
       ov[q] = p.obj[size_t(pj.x + u0) * p.W + (pj.y + u1)];
-      yv[q] = St::load(ys, size_t(jj) * NN + uu, p.inv_scale);
+      yv[q] = St::load_stream(ys, size_t(jj) * NN + uu, p.inv_scale);
     }
 #pragma unroll
     for (int q = 0; q < kProbeUnroll; ++q) {
