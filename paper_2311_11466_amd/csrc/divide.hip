@@ -378,7 +378,9 @@ void divide_fused_kernel(DivideParams p) {
 // ---------------------------------------------------------------------------
 // N = 256: three passes.  A work-group handles 16 rows (or 16 columns) of one
 // pattern, 16 threads per line, 16 values per thread; a line's 256-point DFT
-// is 16 x 16 with one LDS exchange inside the group.
+// is 16 x 16 with one LDS exchange inside the group.  The column pass keeps
+// its exchange tiles interleaved by column ([a][b][column]), so a wave's 16
+// columns touch consecutive LDS words rather than one bank.
 // ---------------------------------------------------------------------------
 constexpr int L256 = 256;
 constexpr int LP = 17;                 // padded pitch of a 16 x 16 exchange tile
@@ -450,9 +452,9 @@ __global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
   static_for<0, 16>([&](auto r1) { v[r1.value] = p.tmp[base + (t + 16 * r1.value) * L256 + col]; });
   dft_reg<16, false>(v);                                  // over r1 -> kr1
   static_for<1, 16>([&](auto k) { v[k.value] = cmul(v[k.value], p.tw[t * k.value]); });
-  static_for<0, 16>([&](auto k) { lds[cl * LT + k.value * LP + t] = v[k.value]; });
+  static_for<0, 16>([&](auto k) { lds[(k.value * LP + t) * 16 + cl] = v[k.value]; });
   __syncthreads();
-  static_for<0, 16>([&](auto r2) { v[r2.value] = lds[cl * LT + t * LP + r2.value]; });
+  static_for<0, 16>([&](auto r2) { v[r2.value] = lds[(t * LP + r2.value) * 16 + cl]; });
   dft_reg<16, false>(v);                                  // over r2 -> kr2; thread t = kr1
   float ef_n = 0.f, ef_d = 0.f;
   const float c = p.c, omc = 1.0f - p.c, inv_n2 = 1.0f / float(L256 * L256);
@@ -464,9 +466,9 @@ __global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
   double acc[2] = {ef_n, ef_d};
   dft_reg<16, true>(v);                                   // over kr2 -> r2
   __syncthreads();
-  static_for<0, 16>([&](auto r2) { lds[cl * LT + t * LP + r2.value] = v[r2.value]; });
+  static_for<0, 16>([&](auto r2) { lds[(t * LP + r2.value) * 16 + cl] = v[r2.value]; });
   __syncthreads();
-  static_for<0, 16>([&](auto k) { v[k.value] = lds[cl * LT + k.value * LP + t]; });  // thread t = r2
+  static_for<0, 16>([&](auto k) { v[k.value] = lds[(k.value * LP + t) * 16 + cl]; });  // thread t = r2
   static_for<1, 16>([&](auto k) { v[k.value] = cmulc(v[k.value], p.tw[t * k.value]); });
   dft_reg<16, true>(v);                                   // over kr1 -> r1
   static_for<0, 16>([&](auto r1) { p.tmp[base + (t + 16 * r1.value) * L256 + col] = v[r1.value]; });
