@@ -201,7 +201,7 @@ def bench(args):
 
     cpu = None
     if not args.no_cpu_baseline:
-        n_cpu = 3
+        n_cpu = 3 if cfg.n <= 128 else 1        # about 3 s (N = 128) or 18 s (N = 256) of host work
         rate, cpu_dt = run_cpu_baseline(scan, abc, n_cpu)
         cpu = {"value": round(rate, 2), "unit": "projections/s", "cores": 1, "kind": "oracle",
                "sample": f"{n_cpu} iterations of the full {cfg.name} workload ({scan.n_pos} patterns), "

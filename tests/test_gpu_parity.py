@@ -320,3 +320,44 @@ def test_fp16_storage_single_step():
     errs = (rel_l2(y0, info["y"]), rel_l2(x1, new.x), rel_l2(o1, new.obj, cov), rel_l2(p1, new.probe))
     say("  fp16 errors y/x/obj/probe", errs)
     assert max(errs) < 1e-3
+
+
+def test_c1_known_probe_then_blind_dc():
+    """The 32-pixel scan's reference run: DC with the probe held for 50
+    iterations, then blind, 200 iterations in all (probe_update_start = 50),
+    against the oracle's same run; bound from the oracle's own drift."""
+    scan = get_scan("tiny_n32")
+    abc = po.preset("DC")
+    n_iter, start = 200, 50
+    say("case: C1 DC, probe held for 50 iterations then updated, 200 iterations")
+    g = gpu_scan(scan, probe_update_start=start)
+    g.set_algorithm(*abc)
+    g.iterate(n_iter)
+    x, y, o, p = (t.cpu().numpy() for t in g.get_state())
+    ef_g = np.array([m["fourier_err"] for m in g.metric_history()])
+    g.close()
+    amp = amp32(scan)
+    cov = covered_mask(scan)
+
+    def run(seed):
+        st = po.init_state(scan.obj0.astype(np.complex64).astype(np.complex128),
+                           scan.probe0.astype(np.complex64).astype(np.complex128), scan.pos)
+        if seed is not None:
+            rng = np.random.default_rng(seed)
+            st.x = st.x * (1 + 1e-7 * rng.standard_normal(st.x.shape))
+        return po.run(st, amp, scan.pos, *abc, n_iter, probe_update_start=start)
+    ref = run(None)
+    ef_r = np.array([m["fourier_err"] for m in ref.history])
+    worst = np.zeros(4)
+    for sd in (1, 2):
+        b = run(sd)
+        ef_b = np.array([m["fourier_err"] for m in b.history])
+        worst = np.maximum(worst, [rel_l2(b.x, ref.x), rel_l2(b.obj, ref.obj, cov), rel_l2(b.probe, ref.probe),
+                                   float(np.max(np.abs(ef_b - ef_r) / ef_r))])
+    tol = np.maximum(20 * worst, 1e-5)
+    errs = np.array([rel_l2(x, ref.x), rel_l2(o, ref.obj, cov), rel_l2(p, ref.probe),
+                     float(np.max(np.abs(ef_g - ef_r) / ef_r))])
+    say("  gpu-vs-oracle x/obj/probe/E_F", errs, "bound", tol)
+    assert np.all(errs <= tol), (errs, tol)
+    # the probe is untouched while held
+    assert ef_g[-1] < ef_g[0]
