@@ -257,10 +257,13 @@ typedef enum {
   PTY_K_COUNT = 6
 } pty_kernel_class;
 
-/* Per-kernel timing with HIP events recorded on the scan's stream around
- * every launch of pty_iterate / pty_iterate_many.  enable = 1 starts timing
- * and clears the totals; 0 stops it.  Timing adds two event records per
- * launch and nothing else. */
+/* Per-kernel timing with HIP events recorded on the scan's stream around the
+ * launches of pty_iterate / pty_iterate_many (and the other iterating calls).
+ * enable = m > 0 starts timing and clears the totals: the launches of every
+ * m-th iteration (iteration count divisible by m) are timed, so m = 1 times
+ * every launch; 0 stops it.  Timing adds two event records per timed launch
+ * and nothing else; each pair costs a few microseconds of device time, which
+ * sampling (m > 1) spreads thin. */
 pty_status pty_profile(pty_scan *scan, int32_t enable);
 
 /* Synchronise, then give per class the total milliseconds and the number of

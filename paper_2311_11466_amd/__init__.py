@@ -322,9 +322,10 @@ class Scan:
         ptrs = [ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p() for t in ts]
         _check(self._L.pty_set_state(self._h, *ptrs, 1), "pty_set_state")
 
-    def profile(self, enable: bool = True):
-        """Start (clearing totals) or stop per-kernel HIP-event timing."""
-        _check(self._L.pty_profile(self._h, int(bool(enable))), "pty_profile")
+    def profile(self, enable: bool = True, every: int = 1):
+        """Start (clearing totals) or stop per-kernel HIP-event timing; with
+        every = m the launches of every m-th iteration are timed."""
+        _check(self._L.pty_profile(self._h, int(every) if enable else 0), "pty_profile")
 
     def profile_read(self):
         """{kernel class: (total ms, launches)} since profile(True)."""

@@ -137,6 +137,7 @@ struct pty_scan {
   bool failed = false;
   // per-kernel event timing
   bool prof = false;
+  int prof_every = 1;               // time the launches of every prof_every-th iteration
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_class;        // class of each (start, end) pair queued
   size_t ev_used = 0;               // events handed out from ev_pool
@@ -169,7 +170,7 @@ pty_status check_usable(const pty_scan* s) {
 // Record an event pair around one launch when timing is on.
 template <class F>
 hipError_t timed(pty_scan* s, int cls, F&& launch) {
-  if (!s->prof) return launch();
+  if (!s->prof || s->k % s->prof_every != 0) return launch();
   auto next = [&](hipEvent_t* e) -> hipError_t {
     if (s->ev_used == s->ev_pool.size()) {
       hipEvent_t ne;
@@ -1029,7 +1030,7 @@ pty_status pty_set_state(pty_scan* scan, const float* x, const float* y, const f
 pty_status pty_profile(pty_scan* scan, int32_t enable) {
   pty_status st = check_usable(scan);
   if (st != PTY_OK) return st;
-  if (enable != 0 && enable != 1) return fail(PTY_ERR_INVALID_ARG, "enable must be 0 or 1");
+  if (enable < 0) return fail(PTY_ERR_INVALID_ARG, "enable must be >= 0");
   PTY_HIP(scan, drain_profile(scan), "profile drain");
   if (enable) {
     for (int i = 0; i < PTY_K_COUNT; ++i) {
@@ -1038,6 +1039,7 @@ pty_status pty_profile(pty_scan* scan, int32_t enable) {
     }
   }
   scan->prof = enable != 0;
+  scan->prof_every = enable > 0 ? enable : 1;
   return PTY_OK;
 }
 

@@ -101,3 +101,19 @@ def test_sp_single_position():
     errs = (rel_l2(o, ro, covered_mask(scan)), rel_l2(p, rp))
     say("  errors", errs)
     assert max(errs) <= 1e-5
+
+
+def test_sampled_profile(tiny):
+    """pty_profile(m): the launches of every m-th iteration are timed."""
+    say("case: sampled event timing")
+    g = gpu_scan(tiny)
+    g.profile(True, every=4)
+    g.iterate(9)                    # iterations 0..8: 0, 4 and 8 are timed
+    prof = g.profile_read()
+    g.profile(False)
+    assert prof["divide"][1] == 3 and prof["object"][1] == 3 and prof["final"][1] == 3, prof
+    assert all(ms > 0 for ms, n in prof.values() if n)
+    g.profile(True)
+    g.iterate(2)
+    assert g.profile_read()["divide"][1] == 2
+    g.close()
