@@ -57,7 +57,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{workload}.json"
 # about 29 us per N = 128 iteration (13 %) to the throughput it measures.
 PROFILE_EVERY = 16
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_11466_amd", "csrc", f)
-                  for f in ("divide.hip", "concur.hip", "common.hpp", "params.hpp")]
+                  for f in ("divide.hip", "divide_fused.hpp", "divide_ops.hpp", "divide_n32.hip", "divide_n64.hip",
+                            "divide_n128.hip", "concur.hip", "common.hpp", "params.hpp")]
 
 
 def kernel_source_hash() -> str:

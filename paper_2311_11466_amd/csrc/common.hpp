@@ -280,7 +280,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
   }
   __syncthreads();
   // one value at a time for many waves (NV * NW loads in flight would spill)
-#pragma unroll(NW > 4 ? 1 : NV)
+  constexpr int kUnrollQ = NW > 4 ? 1 : NV;
+#pragma unroll kUnrollQ
   for (int q = 0; q < NV; ++q) {
     double s = 0.0;
 #pragma unroll

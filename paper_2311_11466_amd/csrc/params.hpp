@@ -137,7 +137,6 @@ struct FlushParams {
 };
 
 // ---- launchers (return hipGetLastError() of the launch) ----
-hipError_t launch_divide(int n, int fp16, const DivideParams& p, int n_patterns, hipStream_t s);
 // one kernel of the divide: stage 0 (fused, or N = 256 rows forward), 1 (N = 256 columns), 2 (N = 256 rows inverse)
 hipError_t launch_divide_stage(int n, int fp16, const DivideParams& p, int n_patterns, int stage, hipStream_t s);
 int divide_stages(int n);
@@ -150,6 +149,13 @@ hipError_t launch_probe_final(const FinalParams& p, int update_probe, hipStream_
 hipError_t launch_metric_slices(const MetricParams& p, hipStream_t s);
 hipError_t launch_swap(float2* a, float2* b, size_t count, hipStream_t s);
 hipError_t launch_sp_batch(int n, const DivideParams& p, int count, hipStream_t s);
+// the fused divide and the sequential-projection batch kernel per size (divide_n*.hip)
+hipError_t launch_fused_n32(int fp16, const DivideParams& p, int n_patterns, hipStream_t s);
+hipError_t launch_fused_n64(int fp16, const DivideParams& p, int n_patterns, hipStream_t s);
+hipError_t launch_fused_n128(int fp16, const DivideParams& p, int n_patterns, hipStream_t s);
+hipError_t launch_sp_n32(const DivideParams& p, int count, hipStream_t s);
+hipError_t launch_sp_n64(const DivideParams& p, int count, hipStream_t s);
+hipError_t launch_sp_n128(const DivideParams& p, int count, hipStream_t s);
 hipError_t launch_sp_probe(const SpProbeParams& p, hipStream_t s);
 // min over complex g of sum |t - g o|^2 / sum |t|^2 over the box [r0, r0+h) x [c0, c0+w)
 // of o (row pitch ow) against t ([h][w]); part holds 4 (blocks + 1) doubles, the
