@@ -60,7 +60,8 @@ typedef enum {
   PTY_ERR_OUT_OF_MEMORY = 2, /* workspace too small                          */
   PTY_ERR_DEVICE = 3,        /* a HIP call failed; the scan is now unusable  */
   PTY_ERR_BAD_STATE = 4,     /* call not valid in the scan's current state   */
-  PTY_ERR_DIVERGED = 5,      /* a metric of the last iteration is not finite */
+  PTY_ERR_DIVERGED = 5,      /* the last iteration's Fourier error is not finite
+                                (or another metric is infinite)               */
   PTY_ERR_UNSUPPORTED = 6    /* valid request this build does not implement  */
 } pty_status;
 
@@ -221,7 +222,10 @@ pty_status pty_get_object(pty_scan *scan, float *dst, size_t n_floats, int32_t d
 pty_status pty_get_probe(pty_scan *scan, float *dst, size_t n_floats, int32_t dst_on_device);
 
 /* Metrics of the last completed iteration.  PTY_ERR_BAD_STATE before the
- * first iteration; PTY_ERR_DIVERGED (with *out filled) if one is not finite. */
+ * first iteration; PTY_ERR_DIVERGED (with *out filled) if the Fourier error is
+ * not finite or another metric is infinite.  A NaN consistency or change
+ * error marks a metric that iteration did not form (blend form, sequential
+ * projections), not divergence. */
 pty_status pty_get_metrics(pty_scan *scan, pty_metrics *out);
 
 /* Up to cap most recent entries, oldest first; *n_out receives the count. */

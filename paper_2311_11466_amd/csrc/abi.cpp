@@ -654,13 +654,19 @@ pty_status pty_set_algorithm(pty_scan* scan, double a, double b, double c) {
 }
 
 pty_status pty_set_algorithm_named(pty_scan* scan, int32_t algorithm, double param) {
-  pty_status st = check_usable(scan);
-  if (st != PTY_OK) return st;
-  if (!std::isfinite(param)) return fail(PTY_ERR_INVALID_ARG, "param must be finite");
-  double a, b, c;
-  st = named_abc(algorithm, param, &a, &b, &c);
-  if (st != PTY_OK) return st;
-  return pty_set_algorithm(scan, a, b, c);
+  try {
+    pty_status st = check_usable(scan);
+    if (st != PTY_OK) return st;
+    if (!std::isfinite(param)) return fail(PTY_ERR_INVALID_ARG, "param must be finite");
+    double a, b, c;
+    st = named_abc(algorithm, param, &a, &b, &c);
+    if (st != PTY_OK) return st;
+    return pty_set_algorithm(scan, a, b, c);
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
+  }
 }
 
 pty_status pty_iterate(pty_scan* scan, int32_t n) {
@@ -726,11 +732,17 @@ pty_status pty_iterate_schedule(pty_scan* scan, const double* abc, int32_t n) {
 }
 
 pty_status pty_set_concur_sweeps(pty_scan* scan, int32_t sweeps) {
-  pty_status st = check_usable(scan);
-  if (st != PTY_OK) return st;
-  if (sweeps < 1 || sweeps > kMaxSweeps) return fail(PTY_ERR_INVALID_ARG, "sweeps must be in [1, 64]");
-  scan->sweeps = sweeps;
-  return PTY_OK;
+  try {
+    pty_status st = check_usable(scan);
+    if (st != PTY_OK) return st;
+    if (sweeps < 1 || sweeps > kMaxSweeps) return fail(PTY_ERR_INVALID_ARG, "sweeps must be in [1, 64]");
+    scan->sweeps = sweeps;
+    return PTY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
+  }
 }
 
 pty_status pty_shadow(pty_scan* scan, float* obj_out, float* probe_out) {
@@ -797,106 +809,124 @@ static std::vector<std::vector<int>> sp_batches(const std::vector<int>& pos, con
 }
 
 pty_status pty_sp_iterate(pty_scan* scan, const int32_t* order, int32_t max_batch, double alpha, double beta) {
-  pty_status st = check_usable(scan);
-  if (st != PTY_OK) return st;
-  if (scan->N > 128) return fail(PTY_ERR_UNSUPPORTED, "sequential projections are built for N <= 128");
-  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(PTY_ERR_INVALID_ARG, "alpha, beta must be finite");
-  if (max_batch < 0) return fail(PTY_ERR_INVALID_ARG, "max_batch must be >= 0");
-  const int J = scan->J, N = scan->N;
-  // the probe steps of a batch (up to J of N^2 complex float32) live in the
-  // exit-wave buffers x and y, which are adjacent
-  if (size_t(J) * N * N * 8 > scan->L.y + size_t(J) * N * N * scan->L.elem_bytes - scan->L.x)
-    return fail(PTY_ERR_DEVICE, "internal: exit-wave buffers too small for the probe steps");
-  std::vector<int> ord(J);
-  if (order) {
-    std::vector<char> seen(J, 0);
-    for (int i = 0; i < J; ++i) {
-      const int j = order[i];
-      if (j < 0 || j >= J || seen[j]) return fail(PTY_ERR_INVALID_ARG, "order must be a permutation of 0..J-1");
-      seen[j] = 1;
-      ord[i] = j;
-    }
-  } else {
-    for (int i = 0; i < J; ++i) ord[i] = i;
-  }
   try {
-    st = flush(scan, false);                  // metrics of the previous iteration, if pending
+    pty_status st = check_usable(scan);
     if (st != PTY_OK) return st;
-    const auto batches = sp_batches(scan->hpos, ord, N, max_batch);
-    scan->sp_members.clear();
-    for (const auto& b : batches) scan->sp_members.insert(scan->sp_members.end(), b.begin(), b.end());
-    const hipStream_t s = scan->stream;
-    int* d_list = scan->at<int>(scan->L.sp_list);
-    PTY_HIP(scan, hipMemcpyAsync(d_list, scan->sp_members.data(), size_t(J) * 4, hipMemcpyHostToDevice, s),
-            "batch lists");
-    const bool blind = scan->blind && scan->k >= scan->probe_update_start;
-    DivideParams p = divide_params(scan);
-    p.alpha = 1.f;                            // psi = P S_j O
-    p.c = 1.0f;
-    p.obj_out = scan->at<float2>(scan->L.obj);
-    p.contrib = scan->at<float2>(scan->L.x);  // x and y hold no state during sequential projections
-    p.pmax_part = scan->at<float>(scan->L.pmax);
-    p.npb = scan->L.npb;
-    p.sp_alpha = float(alpha);
-    p.sp_beta = float(beta);
-    p.sp_blind = blind;
-    SpProbeParams q{};
-    q.probe = scan->at<float2>(scan->L.probe);
-    q.contrib = p.contrib;
-    q.N = N;
-    q.pmax_part = scan->at<float>(scan->L.pmax);
-    int off = 0;
-    for (const auto& b : batches) {
-      p.batch = d_list + off;
-      PTY_HIP(scan, timed(scan, PTY_K_DIVIDE, [&] { return launch_sp_batch(N, p, int(b.size()), s); }),
-              "sequential projection launch");
-      if (blind) {
-        q.count = int(b.size());
-        PTY_HIP(scan, timed(scan, PTY_K_PROBE, [&] { return launch_sp_probe(q, s); }), "probe step launch");
+    if (scan->N > 128) return fail(PTY_ERR_UNSUPPORTED, "sequential projections are built for N <= 128");
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(PTY_ERR_INVALID_ARG, "alpha, beta must be finite");
+    if (max_batch < 0) return fail(PTY_ERR_INVALID_ARG, "max_batch must be >= 0");
+    const int J = scan->J, N = scan->N;
+    // the probe steps of a batch (up to J of N^2 complex float32) live in the
+    // exit-wave buffers x and y, which are adjacent
+    if (size_t(J) * N * N * 8 > scan->L.y + size_t(J) * N * N * scan->L.elem_bytes - scan->L.x)
+      return fail(PTY_ERR_DEVICE, "internal: exit-wave buffers too small for the probe steps");
+    std::vector<int> ord(J);
+    if (order) {
+      std::vector<char> seen(J, 0);
+      for (int i = 0; i < J; ++i) {
+        const int j = order[i];
+        if (j < 0 || j >= J || seen[j]) return fail(PTY_ERR_INVALID_ARG, "order must be a permutation of 0..J-1");
+        seen[j] = 1;
+        ord[i] = j;
       }
-      off += int(b.size());
+    } else {
+      for (int i = 0; i < J; ++i) ord[i] = i;
     }
-    MetricParams m = metric_params(scan, 1);
-    m.k_cur = scan->k;
-    PTY_HIP(scan, launch_metric_slices(m, s), "metrics launch");
-    PTY_HIP(scan, launch_probe_final(final_params(scan, m), 0, s), "metrics launch");
-    scan->sp_batches_last = int(batches.size());
-    scan->k += 1;
-    scan->mode = MODE_INIT;                   // the next generalised iteration starts from x = P S_j O
-    scan->x_valid = scan->y_valid = false;
-    scan->prev_metrics_done = true;
+    try {
+      st = flush(scan, false);                  // metrics of the previous iteration, if pending
+      if (st != PTY_OK) return st;
+      const auto batches = sp_batches(scan->hpos, ord, N, max_batch);
+      scan->sp_members.clear();
+      for (const auto& b : batches) scan->sp_members.insert(scan->sp_members.end(), b.begin(), b.end());
+      const hipStream_t s = scan->stream;
+      int* d_list = scan->at<int>(scan->L.sp_list);
+      PTY_HIP(scan, hipMemcpyAsync(d_list, scan->sp_members.data(), size_t(J) * 4, hipMemcpyHostToDevice, s),
+              "batch lists");
+      const bool blind = scan->blind && scan->k >= scan->probe_update_start;
+      DivideParams p = divide_params(scan);
+      p.alpha = 1.f;                            // psi = P S_j O
+      p.c = 1.0f;
+      p.obj_out = scan->at<float2>(scan->L.obj);
+      p.contrib = scan->at<float2>(scan->L.x);  // x and y hold no state during sequential projections
+      p.pmax_part = scan->at<float>(scan->L.pmax);
+      p.npb = scan->L.npb;
+      p.sp_alpha = float(alpha);
+      p.sp_beta = float(beta);
+      p.sp_blind = blind;
+      SpProbeParams q{};
+      q.probe = scan->at<float2>(scan->L.probe);
+      q.contrib = p.contrib;
+      q.N = N;
+      q.pmax_part = scan->at<float>(scan->L.pmax);
+      int off = 0;
+      for (const auto& b : batches) {
+        p.batch = d_list + off;
+        PTY_HIP(scan, timed(scan, PTY_K_DIVIDE, [&] { return launch_sp_batch(N, p, int(b.size()), s); }),
+                "sequential projection launch");
+        if (blind) {
+          q.count = int(b.size());
+          PTY_HIP(scan, timed(scan, PTY_K_PROBE, [&] { return launch_sp_probe(q, s); }), "probe step launch");
+        }
+        off += int(b.size());
+      }
+      MetricParams m = metric_params(scan, 1);
+      m.k_cur = scan->k;
+      PTY_HIP(scan, launch_metric_slices(m, s), "metrics launch");
+      PTY_HIP(scan, launch_probe_final(final_params(scan, m), 0, s), "metrics launch");
+      scan->sp_batches_last = int(batches.size());
+      scan->k += 1;
+      scan->mode = MODE_INIT;                   // the next generalised iteration starts from x = P S_j O
+      scan->x_valid = scan->y_valid = false;
+      scan->prev_metrics_done = true;
+    } catch (...) {
+      scan->failed = true;
+      return fail(PTY_ERR_DEVICE, "exception during sequential projections");
+    }
+    return PTY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
   } catch (...) {
-    scan->failed = true;
-    return fail(PTY_ERR_DEVICE, "exception during sequential projections");
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
   }
-  return PTY_OK;
 }
 
 int32_t pty_sp_last_batches(const pty_scan* scan) { return scan ? scan->sp_batches_last : -1; }
 
 pty_status pty_object_error(pty_scan* scan, const float* truth, int32_t r0, int32_t c0, int32_t h, int32_t w,
                             double* err) {
-  pty_status st = check_usable(scan);
-  if (st != PTY_OK) return st;
-  if (!truth || !err) return fail(PTY_ERR_INVALID_ARG, "truth and err must be given");
-  if (h < 1 || w < 1 || r0 < 0 || c0 < 0 || r0 + h > scan->H || c0 + w > scan->W)
-    return fail(PTY_ERR_INVALID_ARG, "the box must lie inside the object");
-  double* part = scan->at<double>(scan->L.eval);
-  PTY_HIP(scan, launch_object_error(scan->at<float2>(scan->L.obj), scan->W, reinterpret_cast<const float2*>(truth),
-                                    r0, c0, h, w, part, kEvalBlocks, scan->stream),
-          "object error");
-  double out = 0.0;
-  PTY_HIP(scan, hipMemcpyAsync(&out, part + 4 * kEvalBlocks, 8, hipMemcpyDeviceToHost, scan->stream), "copy");
-  PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
-  *err = out;
-  return PTY_OK;
+  try {
+    pty_status st = check_usable(scan);
+    if (st != PTY_OK) return st;
+    if (!truth || !err) return fail(PTY_ERR_INVALID_ARG, "truth and err must be given");
+    if (h < 1 || w < 1 || r0 < 0 || c0 < 0 || r0 + h > scan->H || c0 + w > scan->W)
+      return fail(PTY_ERR_INVALID_ARG, "the box must lie inside the object");
+    double* part = scan->at<double>(scan->L.eval);
+    PTY_HIP(scan, launch_object_error(scan->at<float2>(scan->L.obj), scan->W, reinterpret_cast<const float2*>(truth),
+                                      r0, c0, h, w, part, kEvalBlocks, scan->stream),
+            "object error");
+    double out = 0.0;
+    PTY_HIP(scan, hipMemcpyAsync(&out, part + 4 * kEvalBlocks, 8, hipMemcpyDeviceToHost, scan->stream), "copy");
+    PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
+    *err = out;
+    return PTY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
+  }
 }
 
 pty_status pty_synchronize(pty_scan* scan) {
-  pty_status st = check_usable(scan);
-  if (st != PTY_OK) return st;
-  PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
-  return PTY_OK;
+  try {
+    pty_status st = check_usable(scan);
+    if (st != PTY_OK) return st;
+    PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
+    return PTY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
+  }
 }
 
 static pty_status get_array(pty_scan* scan, size_t off, size_t floats, float* dst, size_t n_floats, int on_dev) {
@@ -910,13 +940,25 @@ static pty_status get_array(pty_scan* scan, size_t off, size_t floats, float* ds
 }
 
 pty_status pty_get_object(pty_scan* scan, float* dst, size_t n_floats, int32_t dst_on_device) {
-  if (!scan) return fail(PTY_ERR_INVALID_ARG, "scan is NULL");
-  return get_array(scan, scan->L.obj, size_t(scan->H) * scan->W * 2, dst, n_floats, dst_on_device);
+  try {
+    if (!scan) return fail(PTY_ERR_INVALID_ARG, "scan is NULL");
+    return get_array(scan, scan->L.obj, size_t(scan->H) * scan->W * 2, dst, n_floats, dst_on_device);
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
+  }
 }
 
 pty_status pty_get_probe(pty_scan* scan, float* dst, size_t n_floats, int32_t dst_on_device) {
-  if (!scan) return fail(PTY_ERR_INVALID_ARG, "scan is NULL");
-  return get_array(scan, scan->L.probe, size_t(scan->N) * scan->N * 2, dst, n_floats, dst_on_device);
+  try {
+    if (!scan) return fail(PTY_ERR_INVALID_ARG, "scan is NULL");
+    return get_array(scan, scan->L.probe, size_t(scan->N) * scan->N * 2, dst, n_floats, dst_on_device);
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
+  }
 }
 
 static pty_status read_ring(pty_scan* scan, std::vector<double>& ring) {
@@ -929,130 +971,169 @@ static pty_status read_ring(pty_scan* scan, std::vector<double>& ring) {
 }
 
 pty_status pty_get_metrics(pty_scan* scan, pty_metrics* out) {
-  pty_status st = check_usable(scan);
-  if (st != PTY_OK) return st;
-  if (!out) return fail(PTY_ERR_INVALID_ARG, "out is NULL");
-  if (scan->k == 0) return fail(PTY_ERR_BAD_STATE, "no iteration has run");
-  st = flush(scan, false);
-  if (st != PTY_OK) return st;
-  std::vector<double> ring;
-  st = read_ring(scan, ring);
-  if (st != PTY_OK) return st;
-  const int64_t k = scan->k - 1;
-  const double* e = ring.data() + (k % scan->L.cap) * kRingFields;
-  out->iteration = k;
-  out->fourier_err = e[1];
-  out->consistency_err = e[2];
-  out->change = e[3];
-  if (!std::isfinite(e[1]) || (scan->full_metrics && (!std::isfinite(e[2]) || !std::isfinite(e[3]))))
-    return fail(PTY_ERR_DIVERGED, "a metric of the last iteration is not finite");
-  return PTY_OK;
+  try {
+    pty_status st = check_usable(scan);
+    if (st != PTY_OK) return st;
+    if (!out) return fail(PTY_ERR_INVALID_ARG, "out is NULL");
+    if (scan->k == 0) return fail(PTY_ERR_BAD_STATE, "no iteration has run");
+    st = flush(scan, false);
+    if (st != PTY_OK) return st;
+    std::vector<double> ring;
+    st = read_ring(scan, ring);
+    if (st != PTY_OK) return st;
+    const int64_t k = scan->k - 1;
+    const double* e = ring.data() + (k % scan->L.cap) * kRingFields;
+    out->iteration = k;
+    out->fourier_err = e[1];
+    out->consistency_err = e[2];
+    out->change = e[3];
+    // NaN in the consistency or change slot marks a metric that was not formed
+    // (blend form, sequential projections); divergence shows in the Fourier
+    // error, which every iteration forms, or as an infinite metric
+    if (!std::isfinite(e[1]) || std::isinf(e[2]) || std::isinf(e[3]))
+      return fail(PTY_ERR_DIVERGED, "a metric of the last iteration is not finite");
+    return PTY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
+  }
 }
 
 pty_status pty_get_metric_history(pty_scan* scan, pty_metrics* dst, int32_t cap, int32_t* n_out) {
-  pty_status st = check_usable(scan);
-  if (st != PTY_OK) return st;
-  if (!n_out || (cap > 0 && !dst) || cap < 0) return fail(PTY_ERR_INVALID_ARG, "bad dst/cap/n_out");
-  st = flush(scan, false);
-  if (st != PTY_OK) return st;
-  std::vector<double> ring;
-  st = read_ring(scan, ring);
-  if (st != PTY_OK) return st;
-  const int64_t avail = std::min<int64_t>(scan->k, scan->L.cap);
-  const int64_t n = std::min<int64_t>(avail, cap);
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t k = scan->k - n + i;
-    const double* e = ring.data() + (k % scan->L.cap) * kRingFields;
-    dst[i].iteration = k;
-    dst[i].fourier_err = e[1];
-    dst[i].consistency_err = e[2];
-    dst[i].change = e[3];
+  try {
+    pty_status st = check_usable(scan);
+    if (st != PTY_OK) return st;
+    if (!n_out || (cap > 0 && !dst) || cap < 0) return fail(PTY_ERR_INVALID_ARG, "bad dst/cap/n_out");
+    st = flush(scan, false);
+    if (st != PTY_OK) return st;
+    std::vector<double> ring;
+    st = read_ring(scan, ring);
+    if (st != PTY_OK) return st;
+    const int64_t avail = std::min<int64_t>(scan->k, scan->L.cap);
+    const int64_t n = std::min<int64_t>(avail, cap);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t k = scan->k - n + i;
+      const double* e = ring.data() + (k % scan->L.cap) * kRingFields;
+      dst[i].iteration = k;
+      dst[i].fourier_err = e[1];
+      dst[i].consistency_err = e[2];
+      dst[i].change = e[3];
+    }
+    *n_out = int32_t(n);
+    return PTY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
   }
-  *n_out = int32_t(n);
-  return PTY_OK;
 }
 
 int64_t pty_get_iteration(const pty_scan* scan) { return scan ? scan->k : -1; }
 
 pty_status pty_get_state(pty_scan* scan, float* x, float* y, float* obj, float* probe, int32_t on_device) {
-  pty_status st = check_usable(scan);
-  if (st != PTY_OK) return st;
-  if (on_device != 0 && on_device != 1) return fail(PTY_ERR_INVALID_ARG, "on_device must be 0 or 1");
-  if (x) {
-    st = flush(scan, true);
+  try {
+    pty_status st = check_usable(scan);
     if (st != PTY_OK) return st;
-    st = copy_waves_out(scan, scan->L.x, x, on_device);
-    if (st != PTY_OK) return st;
+    if (on_device != 0 && on_device != 1) return fail(PTY_ERR_INVALID_ARG, "on_device must be 0 or 1");
+    if (x) {
+      st = flush(scan, true);
+      if (st != PTY_OK) return st;
+      st = copy_waves_out(scan, scan->L.x, x, on_device);
+      if (st != PTY_OK) return st;
+    }
+    if (y) {
+      st = copy_waves_out(scan, scan->L.y, y, on_device);
+      if (st != PTY_OK) return st;
+    }
+    if (obj) PTY_HIP(scan, hipMemcpyAsync(obj, scan->ws + scan->L.obj, size_t(scan->H) * scan->W * 8,
+                                          kind(1, on_device), scan->stream), "copy object");
+    if (probe) PTY_HIP(scan, hipMemcpyAsync(probe, scan->ws + scan->L.probe, size_t(scan->N) * scan->N * 8,
+                                            kind(1, on_device), scan->stream), "copy probe");
+    PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
+    return PTY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
   }
-  if (y) {
-    st = copy_waves_out(scan, scan->L.y, y, on_device);
-    if (st != PTY_OK) return st;
-  }
-  if (obj) PTY_HIP(scan, hipMemcpyAsync(obj, scan->ws + scan->L.obj, size_t(scan->H) * scan->W * 8,
-                                        kind(1, on_device), scan->stream), "copy object");
-  if (probe) PTY_HIP(scan, hipMemcpyAsync(probe, scan->ws + scan->L.probe, size_t(scan->N) * scan->N * 8,
-                                          kind(1, on_device), scan->stream), "copy probe");
-  PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
-  return PTY_OK;
 }
 
 pty_status pty_set_state(pty_scan* scan, const float* x, const float* y, const float* obj, const float* probe,
                          int32_t on_device) {
-  pty_status st = check_usable(scan);
-  if (st != PTY_OK) return st;
-  if (!x) return fail(PTY_ERR_INVALID_ARG, "x must be given");
-  if (on_device != 0 && on_device != 1) return fail(PTY_ERR_INVALID_ARG, "on_device must be 0 or 1");
-  st = copy_waves_in(scan, scan->L.x, x, on_device);
-  if (st != PTY_OK) return st;
-  if (y) {
-    st = copy_waves_in(scan, scan->L.y, y, on_device);
+  try {
+    pty_status st = check_usable(scan);
     if (st != PTY_OK) return st;
-  } else {
-    PTY_HIP(scan, hipMemsetAsync(scan->ws + scan->L.y, 0, size_t(scan->J) * scan->N * scan->N * scan->L.elem_bytes,
-                                 scan->stream), "clear y");
-  }
-  if (obj) PTY_HIP(scan, hipMemcpyAsync(scan->ws + scan->L.obj, obj, size_t(scan->H) * scan->W * 8,
-                                        kind(on_device, 1), scan->stream), "copy object");
-  if (probe) {
-    PTY_HIP(scan, hipMemcpyAsync(scan->ws + scan->L.probe, probe, size_t(scan->N) * scan->N * 8,
-                                 kind(on_device, 1), scan->stream), "copy probe");
-    st = refresh_probe_max(scan);
+    if (!x) return fail(PTY_ERR_INVALID_ARG, "x must be given");
+    if (on_device != 0 && on_device != 1) return fail(PTY_ERR_INVALID_ARG, "on_device must be 0 or 1");
+    st = copy_waves_in(scan, scan->L.x, x, on_device);
     if (st != PTY_OK) return st;
+    if (y) {
+      st = copy_waves_in(scan, scan->L.y, y, on_device);
+      if (st != PTY_OK) return st;
+    } else {
+      PTY_HIP(scan, hipMemsetAsync(scan->ws + scan->L.y, 0, size_t(scan->J) * scan->N * scan->N * scan->L.elem_bytes,
+                                   scan->stream), "clear y");
+    }
+    if (obj) PTY_HIP(scan, hipMemcpyAsync(scan->ws + scan->L.obj, obj, size_t(scan->H) * scan->W * 8,
+                                          kind(on_device, 1), scan->stream), "copy object");
+    if (probe) {
+      PTY_HIP(scan, hipMemcpyAsync(scan->ws + scan->L.probe, probe, size_t(scan->N) * scan->N * 8,
+                                   kind(on_device, 1), scan->stream), "copy probe");
+      st = refresh_probe_max(scan);
+      if (st != PTY_OK) return st;
+    }
+    PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
+    scan->mode = MODE_MATERIAL;
+    scan->x_valid = true;
+    scan->y_valid = y != nullptr;
+    scan->prev_metrics_done = true;
+    return PTY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
   }
-  PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
-  scan->mode = MODE_MATERIAL;
-  scan->x_valid = true;
-  scan->y_valid = y != nullptr;
-  scan->prev_metrics_done = true;
-  return PTY_OK;
 }
 
 pty_status pty_profile(pty_scan* scan, int32_t enable) {
-  pty_status st = check_usable(scan);
-  if (st != PTY_OK) return st;
-  if (enable < 0) return fail(PTY_ERR_INVALID_ARG, "enable must be >= 0");
-  PTY_HIP(scan, drain_profile(scan), "profile drain");
-  if (enable) {
-    for (int i = 0; i < PTY_K_COUNT; ++i) {
-      scan->prof_ms[i] = 0.0;
-      scan->prof_n[i] = 0;
+  try {
+    pty_status st = check_usable(scan);
+    if (st != PTY_OK) return st;
+    if (enable < 0) return fail(PTY_ERR_INVALID_ARG, "enable must be >= 0");
+    PTY_HIP(scan, drain_profile(scan), "profile drain");
+    if (enable) {
+      for (int i = 0; i < PTY_K_COUNT; ++i) {
+        scan->prof_ms[i] = 0.0;
+        scan->prof_n[i] = 0;
+      }
     }
+    scan->prof = enable != 0;
+    scan->prof_every = enable > 0 ? enable : 1;
+    return PTY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
   }
-  scan->prof = enable != 0;
-  scan->prof_every = enable > 0 ? enable : 1;
-  return PTY_OK;
 }
 
 pty_status pty_profile_read(pty_scan* scan, double* ms, int64_t* launches, int32_t n) {
-  pty_status st = check_usable(scan);
-  if (st != PTY_OK) return st;
-  if (n < 0 || (n > 0 && (!ms || !launches))) return fail(PTY_ERR_INVALID_ARG, "bad ms/launches/n");
-  PTY_HIP(scan, drain_profile(scan), "profile drain");
-  for (int i = 0; i < n; ++i) {
-    ms[i] = i < PTY_K_COUNT ? scan->prof_ms[i] : 0.0;
-    launches[i] = i < PTY_K_COUNT ? scan->prof_n[i] : 0;
+  try {
+    pty_status st = check_usable(scan);
+    if (st != PTY_OK) return st;
+    if (n < 0 || (n > 0 && (!ms || !launches))) return fail(PTY_ERR_INVALID_ARG, "bad ms/launches/n");
+    PTY_HIP(scan, drain_profile(scan), "profile drain");
+    for (int i = 0; i < n; ++i) {
+      ms[i] = i < PTY_K_COUNT ? scan->prof_ms[i] : 0.0;
+      launches[i] = i < PTY_K_COUNT ? scan->prof_n[i] : 0;
+    }
+    return PTY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
   }
-  return PTY_OK;
 }
 
 void pty_destroy_scan(pty_scan* scan) {

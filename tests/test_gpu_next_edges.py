@@ -117,3 +117,19 @@ def test_sampled_profile(tiny):
     g.iterate(2)
     assert g.profile_read()["divide"][1] == 2
     g.close()
+
+
+def test_metrics_after_sequential_projections(tiny):
+    """After an SP iteration the consistency and change slots are NaN (not
+    formed); pty_get_metrics still reports success."""
+    say("case: metrics after SP")
+    g = gpu_scan(tiny, full_metrics=True)
+    g.iterate(2)
+    g.sp_iterate()
+    m = g.metrics()                         # raises on PTY_ERR_DIVERGED
+    assert np.isfinite(m["fourier_err"]) and np.isnan(m["consistency_err"]) and np.isnan(m["change"])
+    assert m["iteration"] == 2
+    g.iterate(1)
+    m = g.metrics()
+    assert np.isfinite(m["fourier_err"])
+    g.close()
