@@ -8,7 +8,9 @@
 //              projection; since F is linear, c P_D x + (1 - c) x is formed
 //              on the spectrum and needs no copy of x_k
 //   inverse    2-D inverse DFT (mirror of the forward, two exchanges)
-//   epilogue   store y_k
+//   epilogue   store y_k (blend form: also w_k from the x_k kept in
+//              registers; sequential projections: the object step into the
+//              window and the probe step of the batch slot instead)
 //
 // The 2-D DFT of N = 4 M points per axis is split, for both axes, as
 //   r = r2 + M r1,  k = k1 + 4 k2:
@@ -21,8 +23,8 @@
 // wavefront.
 //
 // For N = 256 (512 KiB per pattern, more than one CU's LDS) the divide runs as
-// three passes: rows forward (with the prologue), columns forward + Fourier +
-// columns inverse, rows inverse (with the epilogue).
+// three passes (divide.hip): rows forward (with the prologue), columns
+// forward + Fourier + columns inverse, rows inverse (with the epilogue).
 //
 // This header holds the fused kernel (N <= 128); each size is instantiated in
 // its own translation unit (divide_n32/64/128.hip) so the sizes compile in
