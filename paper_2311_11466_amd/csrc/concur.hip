@@ -188,7 +188,6 @@ __global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
   __shared__ int4 ent[kGroupTiles][kListChunk];
   __shared__ float red[16];
   __shared__ int cnt[kGroupTiles];
-  __shared__ double mred[MF_COUNT * 16];
   const int blk = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
   if (blk >= (p.n_tiles + kGroupTiles - 1) / kGroupTiles) return;
   const int g = threadIdx.x >> 8, lt = threadIdx.x & 255;
@@ -204,7 +203,17 @@ __global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
 
   // ---- the block's independent reads, requested together: metric slice,
   // list bounds, probe, probe maxima, the old object values -----------------
-  metric_slice<1024>(p.mp, blk, mred);
+  // The metric slice (a few entries per block) is summed by the first wave
+  // alone, without a barrier, so its reads go out with the others.
+  const MetricParams& mp = p.mp;
+  const int mtotal = mp.J * mp.nslot;
+  const int mper = (mtotal + mp.slices - 1) / mp.slices;
+  const int mi0 = blk * mper, mi1 = min(mtotal, mi0 + mper);
+  double macc[MF_COUNT];
+#pragma unroll
+  for (int q = 0; q < MF_COUNT; ++q)
+    macc[q] = (threadIdx.x < 64 && mi0 + int(threadIdx.x) < mi1)
+                  ? mp.met[size_t(mi0 + threadIdx.x) * MF_COUNT + q] : 0.0;
   const int e0 = p.tile_off[tc];
   const int len = tile_ok ? p.tile_off[tc + 1] - e0 : 0;
   float2 pst[NN / 1024];
@@ -223,6 +232,20 @@ __global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
 #pragma unroll
   for (int k = 0; k < NN / 1024; ++k) pl[threadIdx.x + 1024 * k] = pst[k];
   if (threadIdx.x == 0) pl[kZero] = make_float2(0.f, 0.f);
+  if (threadIdx.x < 64) {
+    for (int i = mi0 + 64 + int(threadIdx.x); i < mi1; i += 64) {
+#pragma unroll
+      for (int q = 0; q < MF_COUNT; ++q) macc[q] += mp.met[size_t(i) * MF_COUNT + q];
+    }
+#pragma unroll
+    for (int q = 0; q < MF_COUNT; ++q) {
+      for (int off = 32; off >= 1; off >>= 1) macc[q] += __shfl_xor(macc[q], off, 64);
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int q = 0; q < MF_COUNT; ++q) mp.part2[size_t(blk) * MF_COUNT + q] = macc[q];
+    }
+  }
   pm = block_max<1024>(pm, red);      // its barriers also publish pl and cnt
   const double thr = p.tau * double(pm);
   int maxlen = cnt[0];
