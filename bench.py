@@ -53,9 +53,21 @@ def kernel_name(cls: str, n: int) -> str:
     return KERNEL_NAMES[cls]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{workload}.json")
 # Kernel durations come from HIP events around the launches of every 16th
-# iteration of the timed region: an event pair around every launch would add
-# about 29 us per N = 128 iteration (13 %) to the throughput it measures.
+# iteration of the timed region (every iteration of short runs, so that at
+# least eight are timed): an event pair around every launch would add about
+# 29 us per N = 128 iteration (13 %) to the throughput it measures.
 PROFILE_EVERY = 16
+
+
+def profile_every(steps: int) -> int:
+    return max(1, min(PROFILE_EVERY, steps // 8))
+
+
+def sampled_iterations(k0: int, steps: int, every: int) -> int:
+    """Iterations k0 .. k0+steps-1 whose launches the sampled event timing covers."""
+    return sum(1 for k in range(k0, k0 + steps) if k % every == 0)
+
+
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_11466_amd", "csrc", f)
                   for f in ("divide.hip", "divide_fused.hpp", "divide_ops.hpp", "divide_n32.hip", "divide_n64.hip",
                             "divide_n128.hip", "concur.hip", "common.hpp", "params.hpp")]
@@ -160,7 +172,9 @@ def bench(args):
     else:
         g.iterate(args.warmup)
     torch.cuda.synchronize()
-    g.profile(True, every=PROFILE_EVERY)
+    every = profile_every(args.steps)
+    n_sampled = sampled_iterations(g.iteration, args.steps, every)
+    g.profile(True, every=every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if sched is not None:
@@ -182,7 +196,7 @@ def bench(args):
         avg_us = ms / cnt * 1e3
         nbytes = algorithmic_bytes(k, cfg.n, scan.n_pos, abc, True, args.storage, full_metrics)
         kernels[k] = {"avg_us": round(avg_us, 3), "launches": cnt,
-                      "share": round(ms / (dt * 1e3), 4),
+                      "share": round(ms / n_sampled * args.steps / (dt * 1e3), 4),
                       "algorithmic_bytes": nbytes,
                       "GBs": round(nbytes / (avg_us * 1e-6) / 1e9, 1) if nbytes else None}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
@@ -316,7 +330,9 @@ def bench_sp(args):
     for _ in range(args.warmup):
         nb = g.sp_iterate(order, args.sp_max_batch, args.sp_alpha, args.sp_beta)
     torch.cuda.synchronize()
-    g.profile(True, every=PROFILE_EVERY)
+    every = profile_every(args.steps)
+    n_sampled = sampled_iterations(g.iteration, args.steps, every)
+    g.profile(True, every=every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -336,7 +352,8 @@ def bench_sp(args):
             continue
         avg_us = ms / cnt * 1e3
         b = bytes_per.get(k)
-        kernels[names.get(k, k)] = {"avg_us": round(avg_us, 3), "launches": cnt, "share": round(ms / (dt * 1e3), 4),
+        kernels[names.get(k, k)] = {"avg_us": round(avg_us, 3), "launches": cnt,
+                                    "share": round(ms / n_sampled * args.steps / (dt * 1e3), 4),
                                     "algorithmic_bytes": round(b) if b else None,
                                     "GBs": round(b / (avg_us * 1e-6) / 1e9, 1) if b else None}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
