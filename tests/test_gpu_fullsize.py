@@ -116,3 +116,70 @@ def test_sampled_step_large_n256():
     e_x = rel_l2(x1, x_ref)
     print("  next-iterate sample error", e_x, flush=True)
     assert e_x <= TOL
+
+
+@pytest.mark.timeout(300)
+def test_full_two_steps_scan_n128_blend():
+    """The blend form at full size (`bench.py --metrics fourier`): two iterations, the
+    second of which forms x from the stored blend w, against two oracle iterations."""
+    scan = make_scan("scan_n128", intensity_dtype=np.float32)
+    abc = po.preset("RAAR", 0.75)
+    print("case: full-size two steps scan_n128 RAAR, blend form", flush=True)
+    x, o, p = _start_state(scan)
+    g = gpu_scan(scan, full_metrics=False)
+    g.set_state(to_dev(x), None, to_dev(o), to_dev(p))
+    g.set_algorithm(*abc)
+    g.iterate(2)
+    x2, y1, o2, p2 = (t.cpu().numpy() for t in g.get_state())
+    hist = g.metric_history()
+    g.close()
+    amp = amp32(scan)
+    cov = covered_mask(scan)
+
+    def two_steps(x_start):
+        st = po.State(x_start.astype(np.complex128), o.astype(np.complex128), p.astype(np.complex128), 0)
+        s1, i0 = po.step(st, amp, scan.pos, *abc, blind=True)
+        s2, i1 = po.step(s1, amp, scan.pos, *abc, blind=True)
+        return s2, i0, i1
+
+    s2, i0, i1 = two_steps(x)
+    errs = {"y": rel_l2(y1, i1["y"]), "x": rel_l2(x2, s2.x), "obj": rel_l2(o2, s2.obj, cov),
+            "probe": rel_l2(p2, s2.probe)}
+    # the second concur divides by overlap sums that, at the edge of the scanned
+    # area, lie just above the guard (about 5e-11 against 1.6e-11 here), so the
+    # object there amplifies any rounding: bound 20 x the oracle's own change
+    # under a 1e-7 perturbation of the start (at least 1e-5)
+    rng = np.random.default_rng(1)
+    q2, _, qi = two_steps(x * (1 + 1e-7 * rng.standard_normal(x.shape)))
+    drift = {"y": rel_l2(qi["y"], i1["y"]), "x": rel_l2(q2.x, s2.x), "obj": rel_l2(q2.obj, s2.obj, cov),
+             "probe": rel_l2(q2.probe, s2.probe)}
+    tol = {k: max(TOL, 20 * v) for k, v in drift.items()}
+    print("  errors", errs, "bounds", tol, flush=True)
+    assert all(errs[k] <= tol[k] for k in errs), (errs, tol)
+    for m, info in zip(hist, (i0, i1)):
+        ef = info["metrics"]["fourier_err"]
+        assert abs(m["fourier_err"] - ef) <= 1e-4 * ef, (m["fourier_err"], ef)
+
+
+@pytest.mark.timeout(300)
+def test_full_step_scan_n128_fp16():
+    """FP16 exit-wave storage at full size (`bench.py --storage fp16`), from the
+    float16-rounded start; bound 2e-3 (float16 unit roundoff 2^-11 per stored
+    component, a few stores per iteration)."""
+    scan = make_scan("scan_n128", intensity_dtype=np.float32)
+    abc = po.preset("RAAR", 0.75)
+    print("case: full-size single step scan_n128 RAAR, fp16 storage", flush=True)
+    x, o, p = _start_state(scan)
+    g = gpu_scan(scan, storage="fp16")
+    g.set_state(to_dev(x), None, to_dev(o), to_dev(p))
+    xs = g.get_state()[0].cpu().numpy()            # the stored (float16-rounded) start
+    g.set_algorithm(*abc)
+    g.iterate(1)
+    x1, y0, o1, p1 = (t.cpu().numpy() for t in g.get_state())
+    g.close()
+    st = po.State(xs.astype(np.complex128), o.astype(np.complex128), p.astype(np.complex128), 0)
+    new, info = po.step(st, amp32(scan), scan.pos, *abc, blind=True)
+    errs = {"y": rel_l2(y0, info["y"]), "x": rel_l2(x1, new.x),
+            "obj": rel_l2(o1, new.obj, covered_mask(scan)), "probe": rel_l2(p1, new.probe)}
+    print("  errors", errs, flush=True)
+    assert max(errs.values()) < 2e-3, errs
