@@ -495,7 +495,7 @@ def main():
     ap.add_argument("--metrics", default="all", choices=["all", "fourier"],
                     help="all: Fourier, consistency and change errors every iteration; "
                          "fourier: the Fourier error only (enables the blend form)")
-    ap.add_argument("--requests", type=int, default=32, help="served: number of requests")
+    ap.add_argument("--requests", type=int, default=256, help="served: number of requests")
     ap.add_argument("--rate-factor", type=float, default=0.7, help="served: arrival rate / closed-loop capacity")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served: HBM budget")
     ap.add_argument("--slots", type=int, default=32, help="served: concurrent scans")
