@@ -255,7 +255,7 @@ typedef enum {
   PTY_K_DIVIDE = 0,          /* divide, fused (N <= 128) or row forward pass (N = 256) */
   PTY_K_DIVIDE_COLS = 1,     /* N = 256: column pass with the Fourier-space projection  */
   PTY_K_DIVIDE_ROWS_INV = 2, /* N = 256: row inverse pass                                */
-  PTY_K_OBJECT = 3,          /* concur, object (and the metric finalisation)             */
+  PTY_K_OBJECT = 3,          /* concur, object (and the sums of metric slices)           */
   PTY_K_PROBE = 4,           /* concur, probe partial sums                               */
   PTY_K_FINAL = 5,           /* probe finalisation and the metric history entry          */
   PTY_K_COUNT = 6
@@ -271,7 +271,7 @@ typedef enum {
 pty_status pty_profile(pty_scan *scan, int32_t enable);
 
 /* Synchronise, then give per class the total milliseconds and the number of
- * launches timed since pty_profile(scan, 1).  ms and launches hold n entries;
+ * launches timed since timing was last started (pty_profile with m > 0).  ms and launches hold n entries;
  * n may be smaller than PTY_K_COUNT. */
 pty_status pty_profile_read(pty_scan *scan, double *ms, int64_t *launches, int32_t n);
 
