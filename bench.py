@@ -494,7 +494,7 @@ def main():
     ap.add_argument("--param-end", type=float, default=0.3)
     ap.add_argument("--metrics", default="all", choices=["all", "fourier"],
                     help="all: Fourier, consistency and change errors every iteration; "
-                         "fourier: the Fourier error only (enables the blend form)")
+                         "fourier: the Fourier error only (N <= 64: enables the blend form)")
     ap.add_argument("--requests", type=int, default=256, help="served: number of requests")
     ap.add_argument("--rate-factor", type=float, default=0.7, help="served: arrival rate / closed-loop capacity")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served: HBM budget")

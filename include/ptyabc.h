@@ -99,7 +99,7 @@ typedef struct {
                                  would not need them); 0: the Fourier error
                                  every iteration, the other two only where
                                  their inputs are read anyway (else NaN).
-                                 With 0, N <= 128 and a != 1, b != 1 the
+                                 With 0, N <= 64 and a != 1, b != 1 the
                                  library keeps w = (1-a) x + a(1-b) y in place
                                  of x between iterations (one read fewer per
                                  pixel); consistency and change are then NaN.

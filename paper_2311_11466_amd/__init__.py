@@ -366,10 +366,10 @@ def workspace_bytes(n: int, n_pos: int, obj_h: int, obj_w: int, storage: str = "
 
 def uses_blend_form(n: int, a: float, b: float, full_metrics: bool) -> bool:
     """Whether the library keeps w = (1-a) x + a(1-b) y in place of x between
-    iterations (the same rule as the library: no full metrics, N <= 128, and
+    iterations (the same rule as the library: no full metrics, N <= 64, and
     both coefficients non-zero in float32)."""
     import numpy as np
-    return (not full_metrics and n <= 128 and np.float32(1.0 - a) != 0
+    return (not full_metrics and n <= 64 and np.float32(1.0 - a) != 0
             and np.float32(a * (1.0 - b)) != 0)
 
 

@@ -307,8 +307,11 @@ pty_status launch_concur(pty_scan* s, const MetricParams& mp, bool update_probe,
 // the next prologue when x and y are both needed, i.e. a != 1 and b != 1.
 // It leaves no x_k for the change metric, so it is used only without
 // full_metrics, and only by the fused divide (N <= 128).
+// The blend form saves a read per pixel but keeps x_k in registers through
+// the transforms; at N = 128 that rules out the two patterns per CU of the
+// x form's split exchanges, which measured faster, so it is used for N <= 64.
 bool use_blend(const pty_scan* s) {
-  return !s->full_metrics && s->N <= 128 && float(1.0 - s->a) != 0.f && float(s->a * (1.0 - s->b)) != 0.f;
+  return !s->full_metrics && s->N <= 64 && float(1.0 - s->a) != 0.f && float(s->a * (1.0 - s->b)) != 0.f;
 }
 
 pty_status launch_iteration(pty_scan* s) {

@@ -104,6 +104,22 @@ struct DivGeom {
   static constexpr int PA = M * 17;        // A <-> B plane (r2): entry c2 * 17 + kk
   static constexpr int PB = 16 * M + 16;   // B <-> C plane (c2): entry kr2 * 16 + kk, padded
   static constexpr int LDS = M * (PA > PB ? PA : PB);   // N = 128: 136 KiB, one pattern per CU
+  // Split exchanges (N = 128): each runs in two passes over half the data, so
+  // the work-group needs 68 KiB of LDS and two patterns share a CU, one's
+  // transforms overlapping the other's memory traffic.  A <-> B passes take
+  // the planes r2 of one stage-A set.  B <-> C is, for each kk, a transpose of
+  // M rows (the threads) by M values; in pass h the thread of row r moves the
+  // half u xor h of its values, u = r / (M/2): a symmetric choice, so every
+  // thread receives exactly into the registers it has just sent.  Threads
+  // with u = 1 (a uniform half of the work-group) hold their stage-B spectrum
+  // and their stage-C sequence with the two halves swapped, so that every
+  // thread sends and receives registers [h M/2, (h+1) M/2) in pass h: negating
+  // the odd inputs of an M-point DFT swaps the halves of its output, and a
+  // half-swapped input multiplies the output by (-1)^k.  Both are exact (the
+  // butterflies are symmetric under a change of sign), and the modulus
+  // projection commutes with the sign except where it sets the phase to zero.
+  static constexpr int PB2 = (M / 2) * 16 + 16;   // B <-> C plane of one pass: entry (k % (M/2)) * 16 + kk
+  static constexpr int LDS_SPLIT = (M / 2) * PA > M * PB2 ? (M / 2) * PA : M * PB2;
 #ifndef PTY_PROLOGUE_GROUP
 #define PTY_PROLOGUE_GROUP 8
 #endif
@@ -111,13 +127,23 @@ struct DivGeom {
   static_assert(SA >= 1 && SB >= 1 && SA * 16 == E && SB * M == E, "geometry");
 };
 
+// Modes that run with split exchanges: N = 128, x form (the blend and SP
+// forms keep x_k in registers and cannot share a CU anyway), compile-time
+// buffer flags.
+template <int N, int MODE>
+constexpr bool split_exchange() {
+  return N == 128 && MODE != PRO_FLAGS && !Pro<MODE>::wf;
+}
+
 template <int N, int T, class St, int MODE>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(split_exchange<N, MODE>() ? 4 : 2)))
 void divide_fused_kernel(DivideParams p) {
   using G = DivGeom<N, T>;
   using PR = Pro<MODE>;
-  constexpr int M = G::M, E = G::E, SA = G::SA, SB = G::SB, PA = G::PA, PB = G::PB;
-  __shared__ float2 lds[G::LDS];
+  constexpr int M = G::M, E = G::E, SA = G::SA, SB = G::SB, PA = G::PA, PB = G::PB, PB2 = G::PB2;
+  constexpr bool SPLIT = split_exchange<N, MODE>();
+  static_assert(!SPLIT || (SA == 2 && SB == 1 && T / M == M / 2), "split exchange geometry");
+  __shared__ float2 lds[SPLIT ? G::LDS_SPLIT : G::LDS];
   __shared__ double red[MF_COUNT * (T / 64)];
 
   const unsigned tid = threadIdx.x;
@@ -203,35 +229,71 @@ void divide_fused_kernel(DivideParams p) {
   };
   // ---- exchange A -> B: element (r2, kk, c2) at plane r2, entry c2*17 + kk --
   static_for<0, SA>([&](auto s) { prologue_and_stage_a(s); });
-  static_for<0, SA>([&](auto s) {
-    const unsigned qa = tid + T * s.value;
-    const unsigned r2 = qa / M, c2 = qa % M;
-    static_for<0, 16>([&](auto kk) { lds[r2 * PA + c2 * 17 + kk.value] = v[s.value * 16 + kk.value]; });
-  });
-  __syncthreads();
-  static_for<0, SB>([&](auto s) {
-    const unsigned qb = tid + T * s.value;
-    const unsigned o = (qb / 16) * 17 + qb % 16;
-    static_for<0, M>([&](auto r2) { v[s.value * M + r2.value] = lds[r2.value * PA + o]; });
-  });
-  __syncthreads();
+  if constexpr (SPLIT) {
+    // pass h: set h holds the planes r2 in [h M/2, (h+1) M/2); the values read
+    // land in v[h M/2 ...], which held set h, sent before the barrier
+    static_for<0, 2>([&](auto h) {
+      const unsigned qa = tid + T * h.value;
+      const unsigned r2 = qa / M - h.value * (M / 2), c2 = qa % M;
+      static_for<0, 16>([&](auto kk) { lds[r2 * PA + c2 * 17 + kk.value] = v[h.value * 16 + kk.value]; });
+      __syncthreads();
+      const unsigned o = (tid / 16) * 17 + tid % 16;
+      static_for<0, M / 2>([&](auto r) { v[h.value * (M / 2) + r.value] = lds[r.value * PA + o]; });
+      __syncthreads();
+    });
+  } else {
+    static_for<0, SA>([&](auto s) {
+      const unsigned qa = tid + T * s.value;
+      const unsigned r2 = qa / M, c2 = qa % M;
+      static_for<0, 16>([&](auto kk) { lds[r2 * PA + c2 * 17 + kk.value] = v[s.value * 16 + kk.value]; });
+    });
+    __syncthreads();
+    static_for<0, SB>([&](auto s) {
+      const unsigned qb = tid + T * s.value;
+      const unsigned o = (qb / 16) * 17 + qb % 16;
+      static_for<0, M>([&](auto r2) { v[s.value * M + r2.value] = lds[r2.value * PA + o]; });
+    });
+    __syncthreads();
+  }
   __builtin_amdgcn_sched_barrier(0);
   // ---- stage B forward: DFT over r2 -> kr2 --------------------------------
+  // split exchanges: the upper half of the work-group negates its odd inputs,
+  // so its spectrum comes out with the halves swapped
+  const unsigned hi_half = __builtin_amdgcn_readfirstlane(tid / (T / 2));
+  const float hs = (SPLIT && hi_half != 0) ? -1.0f : 1.0f;
+  if constexpr (SPLIT) {
+    static_for<1, M, 2>([&](auto r) { v[r.value] = make_float2(v[r.value].x * hs, v[r.value].y * hs); });
+  }
   static_for<0, SB>([&](auto s) { dft_reg<M, false, 1, s.value * M>(v); });
   __builtin_amdgcn_sched_barrier(0);
 
   // ---- exchange B -> C: element (c2, kk, kr2) at plane c2, entry kr2*16 + kk
-  static_for<0, SB>([&](auto s) {
-    const unsigned qb = tid + T * s.value;
-    const unsigned c2 = qb / 16, kk = qb % 16;
-    static_for<0, M>([&](auto k) { lds[c2 * PB + k.value * 16 + kk] = v[s.value * M + k.value]; });
-  });
-  __syncthreads();
-  static_for<0, SB>([&](auto s) {
-    const unsigned qc = tid + T * s.value;
-    static_for<0, M>([&](auto c) { v[s.value * M + c.value] = lds[c.value * PB + qc]; });
-  });
-  __syncthreads();
+  if constexpr (SPLIT) {
+    // pass h: row c2 sends registers [h M/2, (h+1) M/2) (its half u xor h of
+    // the spectrum) to plane c2; row kr2 receives the same registers from the
+    // planes c of its half u xor h
+    const unsigned kk = tid % 16, row = tid / 16, rl = row % (M / 2);
+    static_for<0, 2>([&](auto h) {
+      constexpr int b = h.value * (M / 2);
+      const unsigned c0 = (hi_half ^ h.value) * (M / 2);
+      static_for<0, M / 2>([&](auto i) { lds[row * PB2 + i.value * 16 + kk] = v[b + i.value]; });
+      __syncthreads();
+      static_for<0, M / 2>([&](auto i) { v[b + i.value] = lds[(c0 + i.value) * PB2 + rl * 16 + kk]; });
+      __syncthreads();
+    });
+  } else {
+    static_for<0, SB>([&](auto s) {
+      const unsigned qb = tid + T * s.value;
+      const unsigned c2 = qb / 16, kk = qb % 16;
+      static_for<0, M>([&](auto k) { lds[c2 * PB + k.value * 16 + kk] = v[s.value * M + k.value]; });
+    });
+    __syncthreads();
+    static_for<0, SB>([&](auto s) {
+      const unsigned qc = tid + T * s.value;
+      static_for<0, M>([&](auto c) { v[s.value * M + c.value] = lds[c.value * PB + qc]; });
+    });
+    __syncthreads();
+  }
   __builtin_amdgcn_sched_barrier(0);
 
   // ---- stage C forward, Fourier-space relaxed projection, stage C inverse --
@@ -241,27 +303,46 @@ void divide_fused_kernel(DivideParams p) {
     const unsigned qc = tid + T * s.value;
     static_for<0, M>([&](auto kc2) {
       const float A = ab[kc2.value * (4 * N) + qc];
-      v[s.value * M + kc2.value] = fourier_op(v[s.value * M + kc2.value], A, c, omc, inv_n2, ef_n, ef_d);
+      v[s.value * M + kc2.value] = fourier_op(v[s.value * M + kc2.value], A, c, omc, inv_n2, ef_n, ef_d,
+                                              (kc2.value & 1) ? hs : 1.0f);
     });
     dft_reg<M, true, 1, s.value * M>(v);
   });
   __builtin_amdgcn_sched_barrier(0);
 
   // ---- exchange C -> B, mirror of B -> C ------------------------------------
-  static_for<0, SB>([&](auto s) {
-    const unsigned qc = tid + T * s.value;
-    static_for<0, M>([&](auto c) { lds[c.value * PB + qc] = v[s.value * M + c.value]; });
-  });
-  __syncthreads();
-  static_for<0, SB>([&](auto s) {
-    const unsigned qb = tid + T * s.value;
-    const unsigned c2 = qb / 16, kk = qb % 16;
-    static_for<0, M>([&](auto k) { v[s.value * M + k.value] = lds[c2 * PB + k.value * 16 + kk]; });
-  });
-  __syncthreads();
+  if constexpr (SPLIT) {
+    // mirror: row kr2 sends registers [h M/2, (h+1) M/2) to the planes c of
+    // its half u xor h; row c2 receives them (its half u xor h of the spectrum)
+    const unsigned kk = tid % 16, row = tid / 16, rl = row % (M / 2);
+    static_for<0, 2>([&](auto h) {
+      constexpr int b = h.value * (M / 2);
+      const unsigned c0 = (hi_half ^ h.value) * (M / 2);
+      static_for<0, M / 2>([&](auto i) { lds[(c0 + i.value) * PB2 + rl * 16 + kk] = v[b + i.value]; });
+      __syncthreads();
+      static_for<0, M / 2>([&](auto i) { v[b + i.value] = lds[row * PB2 + i.value * 16 + kk]; });
+      __syncthreads();
+    });
+  } else {
+    static_for<0, SB>([&](auto s) {
+      const unsigned qc = tid + T * s.value;
+      static_for<0, M>([&](auto c) { lds[c.value * PB + qc] = v[s.value * M + c.value]; });
+    });
+    __syncthreads();
+    static_for<0, SB>([&](auto s) {
+      const unsigned qb = tid + T * s.value;
+      const unsigned c2 = qb / 16, kk = qb % 16;
+      static_for<0, M>([&](auto k) { v[s.value * M + k.value] = lds[c2 * PB + k.value * 16 + kk]; });
+    });
+    __syncthreads();
+  }
   __builtin_amdgcn_sched_barrier(0);
   // ---- stage B inverse -----------------------------------------------------
+  // (a half-swapped spectrum gives (-1)^r2 times the sequence: undone here)
   static_for<0, SB>([&](auto s) { dft_reg<M, true, 1, s.value * M>(v); });
+  if constexpr (SPLIT) {
+    static_for<1, M, 2>([&](auto r) { v[r.value] = make_float2(v[r.value].x * hs, v[r.value].y * hs); });
+  }
   __builtin_amdgcn_sched_barrier(0);
 
   // ---- exchange B -> A, mirror of A -> B; then per set the conjugate
@@ -329,17 +410,29 @@ void divide_fused_kernel(DivideParams p) {
     }
     __builtin_amdgcn_sched_barrier(0);
   };
-  static_for<0, SB>([&](auto s) {
-    const unsigned qb = tid + T * s.value;
-    const unsigned o = (qb / 16) * 17 + qb % 16;
-    static_for<0, M>([&](auto r2) { lds[r2.value * PA + o] = v[s.value * M + r2.value]; });
-  });
-  __syncthreads();
-  static_for<0, SA>([&](auto s) {
-    const unsigned qa = tid + T * s.value;
-    const unsigned r2 = qa / M, c2 = qa % M;
-    static_for<0, 16>([&](auto kk) { v[s.value * 16 + kk.value] = lds[r2 * PA + c2 * 17 + kk.value]; });
-  });
+  if constexpr (SPLIT) {
+    static_for<0, 2>([&](auto h) {
+      const unsigned o = (tid / 16) * 17 + tid % 16;
+      static_for<0, M / 2>([&](auto r) { lds[r.value * PA + o] = v[h.value * (M / 2) + r.value]; });
+      __syncthreads();
+      const unsigned qa = tid + T * h.value;
+      const unsigned r2 = qa / M - h.value * (M / 2), c2 = qa % M;
+      static_for<0, 16>([&](auto kk) { v[h.value * 16 + kk.value] = lds[r2 * PA + c2 * 17 + kk.value]; });
+      if constexpr (h.value == 0) __syncthreads();
+    });
+  } else {
+    static_for<0, SB>([&](auto s) {
+      const unsigned qb = tid + T * s.value;
+      const unsigned o = (qb / 16) * 17 + qb % 16;
+      static_for<0, M>([&](auto r2) { lds[r2.value * PA + o] = v[s.value * M + r2.value]; });
+    });
+    __syncthreads();
+    static_for<0, SA>([&](auto s) {
+      const unsigned qa = tid + T * s.value;
+      const unsigned r2 = qa / M, c2 = qa % M;
+      static_for<0, 16>([&](auto kk) { v[s.value * 16 + kk.value] = lds[r2 * PA + c2 * 17 + kk.value]; });
+    });
+  }
   if constexpr (PR::sp) {
     // step sizes alpha / max|P|^2 and beta / max|S_j O|^2 (zero when the maximum is zero)
     __shared__ float fred[T / 64];

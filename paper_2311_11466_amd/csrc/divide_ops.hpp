@@ -29,9 +29,10 @@ __device__ __forceinline__ float2 blend_w(float2 x, float2 y, float be, float ga
 // for the inverse transform: X (c A / |X| + 1 - c) / N^2, and c A / N^2 (phase
 // 0) where X = 0.  |X|^2 below the smallest normal float counts as zero.
 // Branch-free (per-component selects, hardware reciprocal square root).
-// Accumulates (|X| - A)^2 and A^2 in float32 per thread.
+// Accumulates (|X| - A)^2 and A^2 in float32 per thread.  zsign (+1 or -1)
+// multiplies the value set where X = 0, for a caller that holds -X.
 __device__ __forceinline__ float2 fourier_op(float2 X, float A, float c, float one_minus_c, float inv_n2,
-                                             float& ef_num, float& ef_den) {
+                                             float& ef_num, float& ef_den, float zsign = 1.0f) {
   const float m2 = fmaf(X.x, X.x, X.y * X.y);
   const bool nz = m2 >= 1.17549435e-38f;
   const float r = __builtin_amdgcn_rsqf(nz ? m2 : 1.0f);
@@ -42,8 +43,8 @@ __device__ __forceinline__ float2 fourier_op(float2 X, float A, float c, float o
   const float cA = c * A;
   const float f = fmaf(cA, r, one_minus_c) * inv_n2;
   float2 out;
-  out.x = nz ? X.x * f : cA * inv_n2;
-  out.y = nz ? X.y * f : 0.0f;
+  out.x = nz ? X.x * f : cA * inv_n2 * zsign;
+  out.y = nz ? X.y * f : 0.0f * zsign;
   return out;
 }
 

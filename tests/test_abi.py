@@ -106,11 +106,12 @@ def test_algorithmic_bytes_model():
     assert pk.algorithmic_bytes_per_projection(128, 0.5, 1.5, storage="fp16") == 28 * 128 * 128 + 4 * 0
     assert pk.algorithmic_bytes_per_projection(64, 1, 1, full_metrics=False) == 28 * 64 * 64
     assert pk.algorithmic_bytes_per_projection(64, 1, 1, blind=False, full_metrics=False) == 20 * 64 * 64
-    # blend form (no full metrics, N <= 128, a != 1, b != 1): w and sqrt(I) in,
+    # blend form (no full metrics, N <= 64, a != 1, b != 1): w and sqrt(I) in,
     # w and y out, then y twice: 44 bytes (float32), 24 (float16)
-    assert pk.algorithmic_bytes_per_projection(128, 0.5, 1.5, full_metrics=False) == 44 * 128 * 128
-    assert pk.algorithmic_bytes_per_projection(128, 0.5, 1.5, storage="fp16", full_metrics=False) == 24 * 128 * 128
-    # N = 256 keeps x (three passes)
+    assert pk.algorithmic_bytes_per_projection(64, 0.5, 1.5, full_metrics=False) == 44 * 64 * 64
+    assert pk.algorithmic_bytes_per_projection(64, 0.5, 1.5, storage="fp16", full_metrics=False) == 24 * 64 * 64
+    # N = 128 and N = 256 keep x (split exchanges; three passes)
+    assert pk.algorithmic_bytes_per_projection(128, 0.5, 1.5, full_metrics=False) == 52 * 128 * 128
     assert pk.algorithmic_bytes_per_projection(256, 0.5, 1.5, full_metrics=False) == 52 * 256 * 256
     # SF (a = 1): the x form reads y only, 36 + 16 bytes
     assert pk.algorithmic_bytes_per_projection(128, 1, 2, full_metrics=False) == 36 * 128 * 128

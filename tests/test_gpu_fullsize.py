@@ -119,12 +119,13 @@ def test_sampled_step_large_n256():
 
 
 @pytest.mark.timeout(300)
-def test_full_two_steps_scan_n128_blend():
-    """The blend form at full size (`bench.py --metrics fourier`): two iterations, the
-    second of which forms x from the stored blend w, against two oracle iterations."""
+def test_full_two_steps_scan_n128_fourier_only():
+    """Fourier-only metrics at full size (`bench.py --metrics fourier`: the x form with
+    the split-exchange divide and no consistency or change partials), two iterations
+    against two oracle iterations."""
     scan = make_scan("scan_n128", intensity_dtype=np.float32)
     abc = po.preset("RAAR", 0.75)
-    print("case: full-size two steps scan_n128 RAAR, blend form", flush=True)
+    print("case: full-size two steps scan_n128 RAAR, Fourier-only metrics", flush=True)
     x, o, p = _start_state(scan)
     g = gpu_scan(scan, full_metrics=False)
     g.set_state(to_dev(x), None, to_dev(o), to_dev(p))
