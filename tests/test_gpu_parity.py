@@ -267,10 +267,14 @@ def test_edge_single_position_exact_object():
     assert rel_l2(o1, new.obj) < TOL and rel_l2(p1, new.probe) < TOL
 
 
-def test_edge_zero_wave_and_zero_data():
-    """x_j = 0 (phase taken as 0: P_D x_j = F^-1 A_j) and I_j = 0 (P_D x_j = 0)."""
-    scan = get_scan("tiny_n32")
-    say("case: zero wave / zero data")
+@pytest.mark.parametrize("cfg", ["tiny_n32", "p128", "p256"])
+def test_edge_zero_wave_and_zero_data(cfg):
+    """x_j = 0 (phase taken as 0: P_D x_j = F^-1 A_j) and I_j = 0 (P_D x_j = 0).
+    At N = 128 every frequency of the zero wave takes the phase-0 value on both
+    halves of the split-exchange work-group (one of which holds the spectrum
+    with odd frequencies negated)."""
+    scan = get_scan(cfg)
+    say("case: zero wave / zero data", cfg)
     inten = scan.intensity.copy()
     inten[5] = 0.0
 
