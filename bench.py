@@ -512,8 +512,8 @@ def main():
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, args.copy_probe_bytes)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the whole scan on a single MI355X "
-              "(multi-GPU sharding is a design, not an implementation); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the whole scan runs on a single MI355X "
+              "(sharding across GPUs is designed, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "served":
         bench_served(args)

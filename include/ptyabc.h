@@ -62,7 +62,7 @@ typedef enum {
   PTY_ERR_BAD_STATE = 4,     /* call not valid in the scan's current state   */
   PTY_ERR_DIVERGED = 5,      /* the last iteration's Fourier error is not finite
                                 (or another metric is infinite)               */
-  PTY_ERR_UNSUPPORTED = 6    /* valid request this build does not implement  */
+  PTY_ERR_UNSUPPORTED = 6    /* valid request the library does not implement */
 } pty_status;
 
 typedef enum {
