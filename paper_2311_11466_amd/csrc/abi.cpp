@@ -58,6 +58,11 @@ bool desc_shape_ok(const pty_scan_desc* d, std::string* why) {
   if (d->n_pos < 1) { *why = "n_pos must be >= 1"; return false; }
   if (d->obj_h < d->n || d->obj_w < d->n) { *why = "object must be at least N x N"; return false; }
   if (int64_t(d->obj_h) * d->obj_w > (int64_t(1) << 31)) { *why = "object too large"; return false; }
+  {
+    // the tile lists are indexed with int: every (position, tile) pair must fit
+    const int64_t per_pos = ((d->n + kTileH - 2) / kTileH + 1) * ((d->n + kTileW - 2) / kTileW + 1);
+    if (int64_t(d->n_pos) * per_pos > int64_t(INT32_MAX)) { *why = "too many positions"; return false; }
+  }
   if (d->storage != PTY_STORE_FP32 && d->storage != PTY_STORE_FP16) { *why = "storage must be 0 or 1"; return false; }
   if (d->blind != 0 && d->blind != 1) { *why = "blind must be 0 or 1"; return false; }
   if (d->probe_update_start < 0) { *why = "probe_update_start must be >= 0"; return false; }

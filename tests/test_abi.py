@@ -56,7 +56,8 @@ def test_workspace_bytes_host_only(lib):
 
 @pytest.mark.parametrize("field,value", [("n", 48), ("n", 512), ("n_pos", 0), ("obj_h", 16),
                                          ("storage", 2), ("blind", 3), ("tau", -1.0),
-                                         ("tau", float("nan")), ("metric_capacity", -1)])
+                                         ("tau", float("nan")), ("metric_capacity", -1),
+                                         ("n_pos", 2 ** 30)])   # (position, tile) pairs beyond int
 def test_invalid_desc_rejected(lib, field, value):
     d = _desc(**{field: value})
     assert lib.pty_workspace_bytes(ctypes.byref(d)) == 0
