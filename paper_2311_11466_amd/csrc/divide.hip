@@ -199,29 +199,61 @@ hipError_t launch_sp_batch(int n, const DivideParams& p, int count, hipStream_t 
   }
 }
 
-__global__ __launch_bounds__(256) void sp_probe_kernel(SpProbeParams p) {
-  __shared__ float red[4];
+// Probe step of one sequential-projection batch: P += the batch's probe
+// contributions, summed in float64.  A work-group owns 256 probe pixels; its
+// four quarters sum four consecutive ranges of batch slots (each in slot
+// order, four loads in flight), and the quarters are added in order, so the
+// result does not depend on timing.  Also writes the group's max |P|^2.
+__global__ __launch_bounds__(1024) void sp_probe_kernel(SpProbeParams p) {
+  __shared__ double part[2][3][256];
+  __shared__ float red[16];
   const int NN = p.N * p.N;
-  const int u = blockIdx.x * 256 + threadIdx.x;
-  float m = 0.f;
+  const int lt = threadIdx.x & 255, q = threadIdx.x >> 8;
+  const int u = blockIdx.x * 256 + lt;
+  const int per = (p.count + 3) / 4;
+  const int k0 = min(p.count, q * per), k1 = min(p.count, k0 + per);
+  double ax = 0.0, ay = 0.0;
   if (u < NN) {
-    double ax = 0.0, ay = 0.0;
-    for (int k = 0; k < p.count; ++k) {
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
+      float2 c[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) c[i] = p.contrib[size_t(k + i) * NN + u];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ax += c[i].x;
+        ay += c[i].y;
+      }
+    }
+    for (; k < k1; ++k) {
       const float2 c = p.contrib[size_t(k) * NN + u];
       ax += c.x;
       ay += c.y;
+    }
+  }
+  if (q > 0) {
+    part[0][q - 1][lt] = ax;
+    part[1][q - 1][lt] = ay;
+  }
+  __syncthreads();
+  float m = 0.f;
+  if (q == 0 && u < NN) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      ax += part[0][i][lt];
+      ay += part[1][i][lt];
     }
     const float2 o = p.probe[u];
     const float2 nv = make_float2(float(double(o.x) + ax), float(double(o.y) + ay));
     p.probe[u] = nv;
     m = cnorm(nv);
   }
-  m = block_max<256>(m, red);
+  m = block_max<1024>(m, red);
   if (threadIdx.x == 0) p.pmax_part[blockIdx.x] = m;
 }
 
 hipError_t launch_sp_probe(const SpProbeParams& p, hipStream_t s) {
-  hipLaunchKernelGGL(sp_probe_kernel, dim3((p.N * p.N + 255) / 256), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(sp_probe_kernel, dim3((p.N * p.N + 255) / 256), dim3(1024), 0, s, p);
   return hipGetLastError();
 }
 
