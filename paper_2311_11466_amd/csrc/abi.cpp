@@ -311,10 +311,9 @@ pty_status launch_concur(pty_scan* s, const MetricParams& mp, bool update_probe,
 // Blend form (x buffer holds w, see MODE_PENDING_W): it saves the y read of
 // the next prologue when x and y are both needed, i.e. a != 1 and b != 1.
 // It leaves no x_k for the change metric, so it is used only without
-// full_metrics, and only by the fused divide (N <= 128).
-// The blend form saves a read per pixel but keeps x_k in registers through
-// the transforms; at N = 128 that rules out the two patterns per CU of the
-// x form's split exchanges, which measured faster, so it is used for N <= 64.
+// full_metrics.  It keeps x_k in registers through the transforms; at
+// N = 128 that rules out the two patterns per CU of the x form's split
+// exchanges, which measured faster, so it is used for N <= 64.
 bool use_blend(const pty_scan* s) {
   return !s->full_metrics && s->N <= 64 && float(1.0 - s->a) != 0.f && float(s->a * (1.0 - s->b)) != 0.f;
 }
