@@ -18,6 +18,20 @@ constexpr int L256 = 256;
 constexpr int LP = 17;                 // padded pitch of a 16 x 16 exchange tile
 constexpr int LT = 16 * LP;            // one line's exchange tile
 
+// The float32 intermediate of the N = 256 passes is streamed once by each
+// pass: non-temporal accesses keep it from displacing the object and probe
+// lines that the gathers reuse.
+__device__ __forceinline__ float2 tmp_load(const float2* p, size_t i) {
+  const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p) + i);
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void tmp_store(float2* p, size_t i, float2 v) {
+  f32x2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(p) + i);
+}
+
 template <class St>
 __global__ __launch_bounds__(256) void rows256_fwd_kernel(DivideParams p) {
   __shared__ float2 lds[16 * LT];
@@ -64,7 +78,7 @@ __global__ __launch_bounds__(256) void rows256_fwd_kernel(DivideParams p) {
   __syncthreads();
   static_for<0, 16>([&](auto c2) { v[c2.value] = lds[rl * LT + t * LP + c2.value]; });
   dft_reg<16, false>(v);                                  // over c2 -> kc2; thread t = kc1
-  static_for<0, 16>([&](auto k2) { p.tmp[base + r * L256 + t + 16 * k2.value] = v[k2.value]; });
+  static_for<0, 16>([&](auto k2) { tmp_store(p.tmp, base + r * L256 + t + 16 * k2.value, v[k2.value]); });
 
   block_sum<MF_COUNT, 256>(acc, red);
   if (tid >= MF_EC_NUM && tid < MF_COUNT)
@@ -81,7 +95,7 @@ __global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
   const size_t base = size_t(j) * L256 * L256;
   float2 v[16];
   // rows r = t + 16 r1
-  static_for<0, 16>([&](auto r1) { v[r1.value] = p.tmp[base + (t + 16 * r1.value) * L256 + col]; });
+  static_for<0, 16>([&](auto r1) { v[r1.value] = tmp_load(p.tmp, base + (t + 16 * r1.value) * L256 + col); });
   dft_reg<16, false>(v);                                  // over r1 -> kr1
   static_for<1, 16>([&](auto k) { v[k.value] = cmul(v[k.value], p.tw[t * k.value]); });
   static_for<0, 16>([&](auto k) { lds[(k.value * LP + t) * 16 + cl] = v[k.value]; });
@@ -103,7 +117,7 @@ __global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
   static_for<0, 16>([&](auto k) { v[k.value] = lds[(k.value * LP + t) * 16 + cl]; });  // thread t = r2
   static_for<1, 16>([&](auto k) { v[k.value] = cmulc(v[k.value], p.tw[t * k.value]); });
   dft_reg<16, true>(v);                                   // over kr1 -> r1
-  static_for<0, 16>([&](auto r1) { p.tmp[base + (t + 16 * r1.value) * L256 + col] = v[r1.value]; });
+  static_for<0, 16>([&](auto r1) { tmp_store(p.tmp, base + (t + 16 * r1.value) * L256 + col, v[r1.value]); });
 
   block_sum<2, 256>(acc, red);
   if (tid < 2) p.met[(size_t(j) * p.nslot + blockIdx.x) * MF_COUNT + tid] = acc[tid];
@@ -121,7 +135,7 @@ __global__ __launch_bounds__(256) void rows256_inv_kernel(DivideParams p) {
   elem* __restrict__ ys = reinterpret_cast<elem*>(p.y);
   float2 v[16];
   // thread t = kc1 holds kc2
-  static_for<0, 16>([&](auto k2) { v[k2.value] = p.tmp[base + r * L256 + t + 16 * k2.value]; });
+  static_for<0, 16>([&](auto k2) { v[k2.value] = tmp_load(p.tmp, base + r * L256 + t + 16 * k2.value); });
   dft_reg<16, true>(v);                                   // over kc2 -> c2
   static_for<0, 16>([&](auto c2) { lds[rl * LT + c2.value * LP + t] = v[c2.value]; });
   __syncthreads();
