@@ -338,6 +338,70 @@ def pin_true_state_is_fixed_point(scan):
         assert m["fourier_err"] < 1e-20 and m["consistency_err"] < 1e-20 and m["change"] < 1e-12
 
 
+# --------------------------------------------------------------------------
+# Metrics and division guards (error lines of Figs. 7-8, read as E_F, E_C and
+# the change; relative guards), against a hand-derived worked example
+# --------------------------------------------------------------------------
+def _golden_metrics():
+    with open(os.path.join(GOLDEN, "metrics_tiny.json")) as fh:
+        return json.load(fh)
+
+
+def _farr(rows):
+    return np.array([[_frac(v) for v in r] for r in rows], dtype=np.float64)
+
+
+def pin_metrics_worked_example():
+    """One step of DC and RAAR(3/4), known and updated probe, on the 2 x 2
+    worked example: E_F, E_C, the change and the new (O, P) equal the values
+    derived by hand."""
+    g = _golden_metrics()
+    s = g["start"]
+    obj0 = _farr(s["object"]).astype(np.complex128)
+    probe0 = _farr(s["probe"]).astype(np.complex128)
+    amp = np.stack([_farr(a) for a in s["amplitude"]])
+    pos = np.array(s["positions"], dtype=np.int32)
+    for case in g["cases"]:
+        a, b, c = (_frac(v) for v in case["abc"])
+        st = po.init_state(obj0, probe0, pos)
+        new, info = po.step(st, amp, pos, a, b, c, blind=case["blind"])
+        m = info["metrics"]
+        name = case["name"]
+        assert m["iteration"] == 0, name
+        assert np.isclose(m["fourier_err"], _frac(case["fourier_err"]), rtol=1e-13, atol=0), (name, m)
+        assert np.isclose(m["consistency_err"], _frac(case["consistency_err"]), rtol=1e-13, atol=0), (name, m)
+        assert np.isclose(m["change"], np.sqrt(_frac(case["change_squared"])), rtol=1e-13, atol=0), (name, m)
+        assert np.allclose(new.obj, _farr(case["object"]), rtol=1e-13, atol=1e-15), name
+        assert np.allclose(new.probe, _farr(case["probe"]), rtol=1e-13, atol=1e-15), name
+
+
+def pin_guards_are_relative():
+    """The guards compare a denominator with tau times max|P|^2 (object) or
+    max|O|^2 (probe): the hand-derived kept/updated pixels, and invariance of
+    both steps under a common rescaling of the exit waves and the probe (or
+    object), which an absolute threshold would break."""
+    g = _golden_metrics()["guard"]
+    pos = np.array(_golden_metrics()["start"]["positions"], dtype=np.int32)
+    oc = g["object_case"]
+    y = np.stack([_farr(v) for v in oc["y"]]).astype(np.complex128)
+    got = po.concur_object(y, np.ones((2, 3), complex), _farr(oc["probe"]).astype(complex), pos)
+    assert np.allclose(got, _farr(oc["expected"]), rtol=1e-13, atol=0), got
+    pc = g["probe_case"]
+    y = np.stack([_farr(v) for v in pc["y"]]).astype(np.complex128)
+    got = po.concur_probe(y, _farr(pc["object"]).astype(complex), np.ones((2, 2), complex), pos)
+    assert np.allclose(got, _farr(pc["expected"]), rtol=1e-13, atol=0), got
+    # scale invariance on a random problem whose smallest denominators straddle
+    # tau at the extreme scales
+    h, w, n, pos, probe, obj, y = _tiny_problem(15)
+    o_ref = po.concur_object(y, obj, probe, pos)
+    p_ref = po.concur_probe(y, obj, probe, pos)
+    for s in (1e-7, 1e7):
+        o_s = po.concur_object(s * y, obj, s * probe, pos)
+        assert np.allclose(o_s, o_ref, rtol=1e-10, atol=1e-12), s
+        p_s = po.concur_probe(s * y, s * obj, probe, pos)
+        assert np.allclose(p_s, p_ref, rtol=1e-10, atol=1e-12), s
+
+
 ALL_PINS = [
     pin_dft_brute_force,
     pin_dft_parseval_delta,
@@ -351,4 +415,6 @@ ALL_PINS = [
     pin_shadow_recovers_the_true_state,
     pin_three_circle_worked_example,
     pin_presets_match_textbook_updates,
+    pin_metrics_worked_example,
+    pin_guards_are_relative,
 ]

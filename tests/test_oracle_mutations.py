@@ -128,6 +128,61 @@ def _shadow_no_divide(state, amp, pos, blind=True, tau=po.DEFAULT_TAU, sweeps=1)
     _, o, p = po.concur(state.x, state.obj, state.probe, pos, tau, bool(blind), sweeps)  # slip: P_D skipped
     return o, p
 
+
+def _step_with(ef_scale=1.0, ef_den_spectrum=False, ec_normalised=True, change_sqrt=True):
+    """A copy of the oracle's step with one slip in its metric block."""
+    def step(state, amp, pos, a, b, c, blind=True, tau=po.DEFAULT_TAU, probe_update_start=0, sweeps=1):
+        amp = np.asarray(amp, dtype=np.float64)
+        update_probe = bool(blind) and state.k >= probe_update_start
+        out = {}
+
+        def concur_op(y):
+            z, o, p = po.concur(y, state.obj, state.probe, pos, tau, update_probe, sweeps)
+            out["obj"], out["probe"], out["z"] = o, p, z
+            return z
+        x = state.x
+        mag = np.abs(po.dft2(x))
+        ef_num = ef_scale * float(np.sum((mag - amp) ** 2))
+        ef_den = float(np.sum(mag * mag)) if ef_den_spectrum else float(np.sum(amp * amp))
+        x_next, y = po.abc_iteration(x, lambda v: po.modulus_projection(v, amp), concur_op, a, b, c)
+        z = out["z"]
+        ec_num = float(np.sum(np.abs(z - y) ** 2))
+        ec_den = float(np.sum(np.abs(y) ** 2)) if ec_normalised else 1.0
+        dx = float(np.sum(np.abs(x_next - x) ** 2)) / float(np.sum(np.abs(x) ** 2))
+        metrics = {"iteration": state.k, "fourier_err": ef_num / ef_den, "consistency_err": ec_num / ec_den,
+                   "change": float(np.sqrt(dx)) if change_sqrt else dx}
+        new = po.State(x_next, out["obj"], out["probe"], state.k + 1, state.history + [metrics])
+        return new, {"y": y, "z": z, "metrics": metrics}
+    return step
+
+
+def _obj_absolute_tau(y, obj, probe, pos, tau=po.DEFAULT_TAU):
+    n = probe.shape[0]
+    num = np.zeros(obj.shape, complex)
+    den = np.zeros(obj.shape)
+    for j, (p, q) in enumerate(np.asarray(pos)):
+        num[p:p + n, q:q + n] += np.conj(probe) * y[j]
+        den[p:p + n, q:q + n] += np.abs(probe) ** 2
+    out = np.array(obj, dtype=complex, copy=True)
+    ok = den > tau                                      # slip: threshold not relative to max|P|^2
+    out[ok] = num[ok] / den[ok]
+    return out
+
+
+def _probe_absolute_tau(y, obj, probe, pos, tau=po.DEFAULT_TAU):
+    n = probe.shape[0]
+    num = np.zeros((n, n), complex)
+    den = np.zeros((n, n))
+    for j, (p, q) in enumerate(np.asarray(pos)):
+        o = obj[p:p + n, q:q + n]
+        num += np.conj(o) * y[j]
+        den += np.abs(o) ** 2
+    out = np.array(probe, dtype=complex, copy=True)
+    ok = den > tau                                      # slip: threshold not relative to max|O|^2
+    out[ok] = num[ok] / den[ok]
+    return out
+
+
 MUTATIONS = {
     "object_no_conj": [("concur_object", _obj_no_conj)],
     "probe_no_conj": [("concur_probe", _probe_no_conj)],
@@ -144,6 +199,12 @@ MUTATIONS = {
     "preset_raar": [("preset", _preset_raar_wrong)],
     "concur_sweeps_stale_probe": [("concur", _concur_stale_probe)],
     "shadow_without_divide": [("shadow", _shadow_no_divide)],
+    "change_without_sqrt": [("step", _step_with(change_sqrt=False))],
+    "fourier_err_doubled": [("step", _step_with(ef_scale=2.0))],
+    "fourier_err_over_spectrum_energy": [("step", _step_with(ef_den_spectrum=True))],
+    "consistency_err_unnormalised": [("step", _step_with(ec_normalised=False))],
+    "object_guard_absolute": [("concur_object", _obj_absolute_tau)],
+    "probe_guard_absolute": [("concur_probe", _probe_absolute_tau)],
 }
 
 
