@@ -8,16 +8,25 @@ float64) and the metric finalisation.  The metric is diffraction-pattern
 projections per second, J * steps / time, with every input resident in HBM
 before the timed region starts.
 
-Default workload: scan_n128 -- object 1024 x 1024, N = 128, J = 1024
-positions (32 x 32 raster, step 28, +-2 jitter), Poisson data at 1e6 photons
+Default workload: large_n256 -- object 4096 x 4096, N = 256, J = 4096
+positions (64 x 64 raster, step 56, +-3 jitter), Poisson data at 1e4 photons
 per pattern, blind RAAR (beta = 0.75), float32 exit waves with float64
-overlap sums.  Inputs are seeded and synthetic (ptysynth).
+overlap sums, all three metrics every iteration.  scan_n128 (object 1024^2,
+N = 128, J = 1024, 1e6 photons) is measured beside it.  Inputs are seeded
+and synthetic (ptysynth).
 
-The roofline figure is for the kernel with the largest share of the step,
-timed with HIP events on the scan's stream over the timed region itself.
+Timing: the timed region holds only the iterations (no per-kernel events);
+kernel durations come from a second pass of the same iterations with a HIP
+event pair on the scan's stream around every launch.  The roofline line is
+the divide (the dominant kernel; at N = 256 its three passes together) at its
+algorithmic bytes: read x, y and sqrt(I), write x and y, 36 B per pattern
+pixel in float32; the whole iteration's fraction at 52 B per pattern pixel
+(blind) is given beside it.  `traffic` is the divide's measured HBM bytes per
+iteration from rocprofv3 FETCH_SIZE / WRITE_SIZE counters (profiles/), null
+if the kernel sources changed since they were taken.
 
-  python bench.py [--steps K] [--warmup W] [--workload scan_n128|large_n256|tiny_n32]
-  python bench.py --summarize-pmc FETCH_CSV WRITE_CSV   (writes the traffic file under profiles/)
+  python bench.py [--steps K] [--warmup W] [--workload large_n256|scan_n128|tiny_n32|served|compare]
+  python bench.py --summarize-pmc FETCH_DIR WRITE_DIR   (writes the traffic files under profiles/)
 """
 from __future__ import annotations
 
@@ -42,6 +51,7 @@ KERNEL_NAMES = {
     "probe": "probe_partial_kernel",
     "final": "probe_final_kernel",
 }
+DIVIDE_CLASSES = ("divide", "divide_cols", "divide_rows_inv")
 
 
 def kernel_name(cls: str, n: int) -> str:
@@ -51,22 +61,10 @@ def kernel_name(cls: str, n: int) -> str:
     if n == 256 and cls == "object":
         return "object_update_kernel"
     return KERNEL_NAMES[cls]
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{workload}.json")
-# Kernel durations come from HIP events around the launches of every 16th
-# iteration of the timed region (every iteration of short runs, so that at
-# least eight are timed): an event pair around every launch would add about
-# 29 us per N = 128 iteration (13 %) to the throughput it measures.
-PROFILE_EVERY = 16
-
-
-def profile_every(steps: int) -> int:
-    return max(1, min(PROFILE_EVERY, steps // 8))
-
-
-def sampled_iterations(k0: int, steps: int, every: int) -> int:
-    """Iterations k0 .. k0+steps-1 whose launches the sampled event timing covers."""
-    return sum(1 for k in range(k0, k0 + steps) if k % every == 0)
-
+PROFILE_STEPS = 50       # iterations of the kernel-timing pass (at most)
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_11466_amd", "csrc", f)
                   for f in ("divide.hip", "divide_fused.hpp", "divide_ops.hpp", "divide_n32.hip", "divide_n64.hip",
@@ -81,58 +79,108 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kind: str, n: int, J: int, abc, blind: bool, storage: str, full_metrics=True):
-    """HBM bytes one launch of a kernel class must move (roofline numerator).
+def algorithmic_bytes(kind: str, n: int, J: int, abc, blind: bool, storage: str, full_metrics: bool, form: str):
+    """Algorithmic HBM bytes of one iteration's kernel class (roofline numerator).
 
-    Per pattern pixel: divide reads x_{k-1}, y_{k-1} (when needed), sqrt(I)
-    (4 B) and writes x_k, y_k; the N = 256 column pass reads and writes its
-    float32 intermediate (16 B) and reads sqrt(I); the row passes read or write
-    the intermediate (8 B) besides the exit waves; the object and probe kernels
-    read y once each.  Object/probe gathers and the float64 partial sums are
-    not counted (they are cache-resident or small).
+    Per pattern pixel, with e the exit-wave element size (8 B float32, 4 B
+    float16): the divide reads x_{k-1} (when 1-a != 0 or the metrics need it),
+    y_{k-1} (when a(1-b) != 0 or the metrics need it) and sqrt(I) (4 B), and
+    writes x_k (same condition as its read) and y_k; in the blend form
+    (form "w") it reads w_{k-1} and sqrt(I) and writes w_k and y_k.  The
+    object and probe steps read y once each (the probe step only when blind).
+    Object and probe gathers and the float64 partial sums are cache-resident
+    or small and are not counted; neither is the float32 intermediate of the
+    N = 256 passes (traffic the method does not need).
     """
-    from paper_2311_11466_amd import uses_blend_form
     a, b, _ = abc
     e = 4 if storage == "fp16" else 8
-    rx = e if (abs(1 - a) > 0 or full_metrics) else 0
-    ry = e if (abs(a * (1 - b)) > 0 or full_metrics) else 0
     nn = n * n * J
     if kind == "divide":
-        if uses_blend_form(n, a, b, full_metrics):
-            return (e + 4 + e + e) * nn             # w_{k-1}, sqrt(I) in; w_k, y_k out
-        if n == 256:
-            return (rx + ry + rx + 8) * nn          # rows forward: x, y in; x out; intermediate out
+        if form == "w":
+            return (e + 4 + e + e) * nn
+        rx = e if (abs(1 - a) > 0 or full_metrics) else 0
+        ry = e if (abs(a * (1 - b)) > 0 or full_metrics) else 0
         return (rx + ry + 4 + rx + e) * nn
-    if kind == "divide_cols":
-        return (8 + 4 + 8) * nn
-    if kind == "divide_rows_inv":
-        return (8 + e) * nn
-    if kind in ("object", "probe"):
+    if kind == "object":
         return e * nn
+    if kind == "probe":
+        return e * nn if blind else 0
     return 0
 
 
 def make_workload(name: str):
     import numpy as np
     from ptysynth import make_scan
-    scan = make_scan(name, intensity_dtype=np.float32)
-    return scan
+    return make_scan(name, intensity_dtype=np.float32)
 
 
-def run_cpu_baseline(scan, abc, n_iter: int):
-    """The FP64 oracle, as it stands, on the same scan for n_iter iterations."""
+# --------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle as it stands
+# --------------------------------------------------------------------------
+def cpu_sample(scan, max_patterns: int):
+    """A bounded sample of the workload for the oracle: the whole scan if it has
+    at most max_patterns patterns, else the leading square block of the raster
+    (its object cropped to the block's windows).  Returns (pos, amp, obj0,
+    probe0, description)."""
+    import numpy as np
+    cfg = scan.config
+    pos = np.asarray(scan.pos)
+    amp = np.sqrt(scan.intensity.astype(np.float64))
+    if scan.n_pos <= max_patterns:
+        return pos, amp, scan.obj0, scan.probe0, f"the whole {cfg.name} scan ({scan.n_pos} patterns)"
+    rows, cols = cfg.raster
+    side = int(np.sqrt(max_patterns))
+    idx = np.array([r * cols + c for r in range(side) for c in range(side)])
+    sub = pos[idx]
+    r0, c0 = sub.min(axis=0)
+    r1, c1 = sub.max(axis=0) + scan.n
+    return (sub - [r0, c0], amp[idx], scan.obj0[r0:r1, c0:c1].copy(), scan.probe0,
+            f"the leading {side} x {side} block of the {cfg.name} raster ({len(idx)} of {scan.n_pos} patterns "
+            f"of {scan.n}^2, object cropped to {r1 - r0} x {c1 - c0})")
+
+
+def _oracle_worker(path, abc, n_iter):
+    """One oracle run of the sample stored at path (a file this benchmark wrote);
+    returns its wall time."""
     import numpy as np
     from oracle import pty_oracle as po
-    amp = np.sqrt(scan.intensity.astype(np.float64))
-    st = po.init_state(scan.obj0, scan.probe0, scan.pos)
+    with np.load(path) as d:
+        pos, amp, obj0, probe0 = d["pos"], d["amp"], d["obj0"], d["probe0"]
+    st = po.init_state(obj0, probe0, pos)
     t0 = time.perf_counter()
-    po.run(st, amp, scan.pos, *abc, n_iter, blind=True)
-    dt = time.perf_counter() - t0
-    return scan.n_pos * n_iter / dt, dt
+    po.run(st, amp, pos, *abc, n_iter, blind=True)
+    return time.perf_counter() - t0
 
 
-def load_traffic(kernel: str, workload: str):
-    path = TRAFFIC_FILE.format(kernel=kernel, workload=workload)
+def run_cpu_baseline(scan, abc, max_patterns: int, n_iter: int):
+    """The oracle on one host core, and as one copy per core on all of them
+    (aggregate projections/s of independent runs of the same sample)."""
+    import multiprocessing as mp
+    import tempfile
+    import numpy as np
+    pos, amp, obj0, probe0, what = cpu_sample(scan, max_patterns)
+    fd, path = tempfile.mkstemp(suffix=".npz", dir="/tmp")
+    os.close(fd)
+    try:
+        np.savez(path, pos=pos, amp=amp, obj0=obj0, probe0=probe0)
+        t1 = _oracle_worker(path, abc, n_iter)
+        one = len(pos) * n_iter / t1
+        cores = max(1, min(16, len(os.sched_getaffinity(0))))
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(cores) as pool:
+            times = pool.starmap(_oracle_worker, [(path, abc, n_iter)] * cores)
+        wall = time.perf_counter() - t0
+        allc = cores * len(pos) * n_iter / max(max(times), 1e-9)
+    finally:
+        os.unlink(path)
+    return {"value": round(allc, 2), "unit": "projections/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_iter} iterations of {what}, FP64 NumPy oracle, one single-threaded copy per core "
+                      f"on {cores} cores ({wall:.1f} s wall; slowest copy {max(times):.1f} s)",
+            "one_core": round(one, 2), "one_core_s": round(t1, 1)}
+
+
+def load_traffic(cls: str, workload: str):
+    path = TRAFFIC_FILE.format(kernel=cls, workload=workload)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -142,15 +190,15 @@ def load_traffic(kernel: str, workload: str):
     return t.get("bytes_per_launch")
 
 
-def bench(args):
+def measure(args, workload: str, steps: int, warmup: int):
+    """Create the scan, run warm-up, the timed region and the kernel-timing
+    pass.  Returns the measurement record (no CPU baseline)."""
     import numpy as np
     import torch
     import paper_2311_11466_amd as pk
 
-    torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    scan = make_workload(args.workload)
-    abc = pk.preset(args.algorithm, args.param)
+    scan = make_workload(workload)
     cfg = scan.config
     full_metrics = args.metrics == "all"
     print(f"# workload {cfg.name}: object {cfg.obj_h}x{cfg.obj_w}, N={cfg.n}, J={scan.n_pos}", file=sys.stderr,
@@ -159,81 +207,124 @@ def bench(args):
                 torch.as_tensor(scan.obj0.astype(np.complex64)).to(dev),
                 torch.as_tensor(scan.probe0.astype(np.complex64)).to(dev),
                 storage=args.storage, blind=True, device=dev, full_metrics=full_metrics)
-    g.set_algorithm(*abc)
+    g.set_algorithm_named(args.algorithm, args.param)
+    abc = pk.algorithm_abc(args.algorithm, args.param)
     g.set_concur_sweeps(args.concur_sweeps)
     sched = None
+    n_prof = min(steps, PROFILE_STEPS)
     if args.schedule == "linear":
         # the preset's parameter (beta or lambda) moves linearly from --param to
-        # --param-end over warm-up and timed iterations
-        n_all = args.warmup + args.steps
-        sched = [pk.preset(args.algorithm, args.param + (args.param_end - args.param) * i / max(n_all - 1, 1))
+        # --param-end over warm-up and timed iterations; the kernel pass repeats
+        # the timed part of the schedule
+        n_all = warmup + steps
+        sched = [pk.algorithm_abc(args.algorithm, args.param + (args.param_end - args.param) * i / max(n_all - 1, 1))
                  for i in range(n_all)]
-        g.iterate_schedule(sched[:args.warmup])
+        g.iterate_schedule(sched[:warmup])
     else:
-        g.iterate(args.warmup)
-    torch.cuda.synchronize()
-    every = profile_every(args.steps)
-    n_sampled = sampled_iterations(g.iteration, args.steps, every)
-    g.profile(True, every=every)
+        g.iterate(warmup)
+    form = g.state_form()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if sched is not None:
-        g.iterate_schedule(sched[args.warmup:])
+        g.iterate_schedule(sched[warmup:])
     else:
-        g.iterate(args.steps)
+        g.iterate(steps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    dt = time.perf_counter() - t0
+    m = g.metrics(allow_diverged=True)
+    print(f"# timed {steps} steps in {dt * 1e3:.2f} ms; last metrics {m}", file=sys.stderr, flush=True)
+    # kernel-timing pass: the same iterations with an event pair around every launch
+    g.profile(True, every=1)
+    if sched is not None:
+        g.iterate_schedule(sched[warmup:warmup + n_prof])
+    else:
+        g.iterate(n_prof)
     prof = g.profile_read()
     g.profile(False)
-    dt = t1 - t0
-    m = g.metrics(allow_diverged=True)
-    print(f"# timed {args.steps} steps in {dt * 1e3:.2f} ms; last metrics {m}", file=sys.stderr, flush=True)
+    g.close()
 
     kernels = {}
     for k, (ms, cnt) in prof.items():
         if cnt == 0:
             continue
-        avg_us = ms / cnt * 1e3
-        nbytes = algorithmic_bytes(k, cfg.n, scan.n_pos, abc, True, args.storage, full_metrics)
-        kernels[k] = {"avg_us": round(avg_us, 3), "launches": cnt,
-                      "share": round(ms / n_sampled * args.steps / (dt * 1e3), 4),
-                      "algorithmic_bytes": nbytes,
-                      "GBs": round(nbytes / (avg_us * 1e-6) / 1e9, 1) if nbytes else None}
-    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
-    d = kernels[dom]
-    traffic = load_traffic(dom, cfg.name)
-    roofline = {"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(d["GBs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kernel_name(dom, cfg.n), "avg_us": d["avg_us"],
-                "algorithmic_bytes_per_launch": d["algorithmic_bytes"]}
+        per_iter_us = ms / n_prof * 1e3
+        kernels[k] = {"kernel": kernel_name(k, cfg.n), "avg_us": round(ms / cnt * 1e3, 3), "launches": cnt,
+                      "us_per_iteration": round(per_iter_us, 3),
+                      "share": round(per_iter_us / (dt / steps * 1e6), 4)}
+    units = {}
+    div = [k for k in DIVIDE_CLASSES if k in kernels]
+    div_us = sum(kernels[k]["us_per_iteration"] for k in div)
+    units["divide"] = (div_us, algorithmic_bytes("divide", cfg.n, scan.n_pos, abc, True, args.storage,
+                                                 full_metrics, form))
+    for k in ("object", "probe"):
+        if k in kernels:
+            units[k] = (kernels[k]["us_per_iteration"],
+                        algorithmic_bytes(k, cfg.n, scan.n_pos, abc, True, args.storage, full_metrics, form))
+    for k, (us, nbytes) in units.items():
+        rec = kernels.setdefault(k, {})
+        if k == "divide" and len(div) > 1:
+            rec = kernels["divide_all_passes"] = {"kernels": [kernels[c]["kernel"] for c in div],
+                                                  "us_per_iteration": round(us, 3)}
+        rec["algorithmic_bytes"] = nbytes
+        rec["GBs"] = round(nbytes / (us * 1e-6) / 1e9, 1) if nbytes else None
+        rec["frac"] = round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if nbytes else None
+    traffic = [load_traffic(c, cfg.name) for c in div]
+    d_us, d_bytes = units["divide"]
+    roofline = {"bound": "hbm", "achieved": round(d_bytes / (d_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(d_bytes / (d_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": (sum(traffic) if all(t is not None for t in traffic) else None),
+                "kernel": " + ".join(kernel_name(c, cfg.n) for c in div), "avg_us": round(d_us, 3),
+                "algorithmic_bytes_per_launch": d_bytes}
+    it_bytes = sum(v[1] for v in units.values())
+    ms_step = dt / steps * 1e3
+    iteration = {"algorithmic_bytes": it_bytes, "ms": round(ms_step, 4),
+                 "achieved_GBs": round(it_bytes / (ms_step * 1e-3) / 1e9, 1),
+                 "frac": round(it_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return {"scan": scan, "cfg": cfg, "abc": abc, "form": form, "full_metrics": full_metrics, "sched": sched,
+            "dt": dt, "steps": steps, "value": scan.n_pos * steps / dt, "ms_per_step": ms_step,
+            "roofline": roofline, "iteration_roofline": iteration, "kernels": kernels, "metrics_last": m,
+            "profile_steps": n_prof}
 
+
+def bench(args):
+    import torch
+    torch.cuda.set_device(0)
+    r = measure(args, args.workload, args.steps, args.warmup)
+    scan, cfg, abc = r["scan"], r["cfg"], r["abc"]
+    also = {}
+    if args.also and args.also != args.workload:
+        o = measure(args, args.also, args.also_steps, args.warmup)
+        also[args.also] = {"value": round(o["value"], 1), "unit": "projections/s", "steps": o["steps"],
+                           "ms_per_step": round(o["ms_per_step"], 4), "roofline": o["roofline"],
+                           "iteration_roofline": o["iteration_roofline"],
+                           "config": {"object": [o["cfg"].obj_h, o["cfg"].obj_w], "n": o["cfg"].n,
+                                      "positions": o["scan"].n_pos}}
+        del o
     if args.copy_probe:
         # a plain elementwise kernel of known traffic (reads 2 B, writes B bytes), for
         # scaling the rocprofv3 FETCH_SIZE / WRITE_SIZE counters
         nf = args.copy_probe_bytes // 4
-        a = torch.ones(nf, dtype=torch.float32, device=dev)
-        b = torch.ones(nf, dtype=torch.float32, device=dev)
-        c = torch.empty(nf, dtype=torch.float32, device=dev)
+        a = torch.ones(nf, dtype=torch.float32, device="cuda")
+        b = torch.ones(nf, dtype=torch.float32, device="cuda")
+        c = torch.empty(nf, dtype=torch.float32, device="cuda")
         for _ in range(3):
             torch.add(a, b, out=c)
         torch.cuda.synchronize()
-
+        del a, b, c
     cpu = None
     if not args.no_cpu_baseline:
-        n_cpu = 3 if cfg.n <= 128 else 1        # about 3 s (N = 128) or 18 s (N = 256) of host work
-        rate, cpu_dt = run_cpu_baseline(scan, abc, n_cpu)
-        cpu = {"value": round(rate, 2), "unit": "projections/s", "cores": 1, "kind": "oracle",
-               "sample": f"{n_cpu} iterations of the full {cfg.name} workload ({scan.n_pos} patterns), "
-                         f"FP64 NumPy oracle, single thread, {cpu_dt:.1f} s"}
-    value = scan.n_pos * args.steps / dt
+        if cfg.n >= 256:
+            cpu = run_cpu_baseline(scan, abc, max_patterns=256, n_iter=6)
+        else:
+            cpu = run_cpu_baseline(scan, abc, max_patterns=1024, n_iter=3 if cfg.n >= 128 else 20)
     line = {
         "metric": "diffraction-pattern projections/s (P_D+P_C) at 1 GPU",
-        "value": round(value, 1),
+        "value": round(r["value"], 1),
         "unit": "projections/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "ms_per_step": round(r["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -243,20 +334,21 @@ def bench(args):
                    "algorithm": f"{args.algorithm}({args.param})" if args.algorithm in ("RAAR", "RRR", "TLAMBDA")
                    else args.algorithm,
                    "abc": list(abc), "blind": True, "storage": args.storage, "accumulate": "fp64",
-                   "metrics": ("fourier, consistency and change errors every iteration" if full_metrics
+                   "metrics": ("fourier, consistency and change errors every iteration" if r["full_metrics"]
                                else "fourier error every iteration"),
-                   "exit_wave_state": "w = (1-a) x + a(1-b) y" if pk.uses_blend_form(cfg.n, abc[0], abc[1],
-                                                                                     full_metrics) else "x",
+                   "exit_wave_state": "w = (1-a) x + a(1-b) y" if r["form"] == "w" else "x",
                    "concur_sweeps": args.concur_sweeps,
                    "schedule": (f"{args.algorithm} parameter linear {args.param} -> {args.param_end}"
-                                if sched is not None else "constant"),
+                                if r["sched"] is not None else "constant"),
                    "photons": cfg.photons, "parallelism": "single GPU"},
-        "roofline": roofline,
+        "roofline": r["roofline"],
+        "iteration_roofline": r["iteration_roofline"],
         "cpu_baseline": cpu,
-        "kernels": kernels,
-        "metrics_last": m,
+        "kernels": r["kernels"],
+        "kernel_timing": f"HIP events around every launch in a separate pass of {r['profile_steps']} iterations",
+        "metrics_last": r["metrics_last"],
+        "also": also,
     }
-    g.close()
     print(json.dumps(line), flush=True)
 
 
@@ -330,17 +422,19 @@ def bench_sp(args):
     for _ in range(args.warmup):
         nb = g.sp_iterate(order, args.sp_max_batch, args.sp_alpha, args.sp_beta)
     torch.cuda.synchronize()
-    every = profile_every(args.steps)
-    n_sampled = sampled_iterations(g.iteration, args.steps, every)
-    g.profile(True, every=every)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         g.sp_iterate(order, args.sp_max_batch, args.sp_alpha, args.sp_beta)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = g.profile_read()
     m = g.metrics(allow_diverged=True)
+    # kernel-timing pass: the same iterations with an event pair around every launch
+    n_sampled = min(args.steps, PROFILE_STEPS)
+    g.profile(True, every=1)
+    for _ in range(n_sampled):
+        g.sp_iterate(order, args.sp_max_batch, args.sp_alpha, args.sp_beta)
+    prof = g.profile_read()
+    g.profile(False)
     g.close()
     nn = cfg.n * cfg.n
     per_batch = scan.n_pos / max(nb, 1)
@@ -477,10 +571,13 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="scan_n128",
-                    choices=["scan_n128", "large_n256", "tiny_n32", "served", "compare"])
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="large_n256",
+                    choices=["large_n256", "scan_n128", "tiny_n32", "served", "compare"])
+    ap.add_argument("--also", default="scan_n128", choices=["scan_n128", "large_n256", "tiny_n32", "none"],
+                    help="a second workload measured in the same run and reported under 'also'")
+    ap.add_argument("--also-steps", type=int, default=100)
     ap.add_argument("--curves-out", default=None, help="compare: write the full error lines here (JSON)")
     ap.add_argument("--method", default="abc", choices=["abc", "sp"],
                     help="abc: the generalised iteration; sp: sequential projections")
@@ -508,6 +605,8 @@ def main():
     ap.add_argument("--copy-probe-bytes", type=int, default=1 << 30)
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.also == "none":
+        args.also = None
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, args.copy_probe_bytes)
         return

@@ -139,6 +139,18 @@ pty_status pty_set_algorithm(pty_scan *scan, double a, double b, double c);
  * and is ignored otherwise. */
 pty_status pty_set_algorithm_named(pty_scan *scan, int32_t algorithm, double param);
 
+/* (a, b, c) of a named algorithm (the table above; param is beta or lambda),
+ * written to abc[0..2].  PTY_ERR_INVALID_ARG for an unknown algorithm, a
+ * non-finite param or abc == NULL.  Needs no scan and no device. */
+pty_status pty_algorithm_abc(int32_t algorithm, double param, double *abc);
+
+/* Which exit-wave state the scan's next iteration keeps between iterations
+ * with its current (a, b, c) and metric setting: 0 the iterate x (52 bytes
+ * per pattern pixel in the blind float32 form), 1 the blend
+ * w = (1-a) x + a(1-b) y (44 bytes; only without full_metrics, for N <= 64,
+ * and when 1-a and a(1-b) are both nonzero in float32).  -1 for NULL. */
+int32_t pty_state_form(const pty_scan *scan);
+
 /* Queue n >= 0 iterations on the scan's stream and return. */
 pty_status pty_iterate(pty_scan *scan, int32_t n);
 

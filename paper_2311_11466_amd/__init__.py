@@ -32,7 +32,7 @@ EXPORTS = [
     "pty_get_metrics", "pty_get_metric_history", "pty_get_iteration", "pty_get_state",
     "pty_set_state", "pty_destroy_scan", "pty_status_string", "pty_last_error",
     "pty_profile", "pty_profile_read", "pty_iterate_schedule", "pty_set_concur_sweeps", "pty_shadow",
-    "pty_object_error", "pty_sp_iterate", "pty_sp_last_batches",
+    "pty_object_error", "pty_sp_iterate", "pty_sp_last_batches", "pty_algorithm_abc", "pty_state_form",
 ]
 KERNEL_CLASSES = ["divide", "divide_cols", "divide_rows_inv", "object", "probe", "final"]
 
@@ -108,6 +108,9 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.POINTER(ctypes.c_double)]
     L.pty_sp_iterate.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_double]
+    L.pty_algorithm_abc.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    L.pty_state_form.argtypes = [P]
+    L.pty_state_form.restype = ctypes.c_int32
     L.pty_sp_last_batches.argtypes = [P]
     L.pty_sp_last_batches.restype = ctypes.c_int32
     L.pty_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
@@ -115,7 +118,8 @@ def load_library(path: str = LIB_PATH):
     for name in ("pty_profile", "pty_profile_read", "pty_create_scan", "pty_set_algorithm", "pty_set_algorithm_named", "pty_iterate",
                  "pty_iterate_many", "pty_synchronize", "pty_get_object", "pty_get_probe",
                  "pty_get_metrics", "pty_get_metric_history", "pty_get_state", "pty_set_state",
-                 "pty_iterate_schedule", "pty_set_concur_sweeps", "pty_shadow", "pty_object_error", "pty_sp_iterate"):
+                 "pty_iterate_schedule", "pty_set_concur_sweeps", "pty_shadow", "pty_object_error", "pty_sp_iterate",
+                 "pty_algorithm_abc"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -131,15 +135,12 @@ def _torch():
     return torch
 
 
-def preset(name: str, param: float = 0.0):
-    """(a, b, c) of a named algorithm, as the library uses them."""
-    name = name.upper()
-    table = {
-        "DC": (1.0, 1.0, 1.0), "AR": (1.0, 1.0, 2.0), "DR": (0.5, 2.0, 2.0), "SF": (1.0, 2.0, 1.0),
-        "RAAR": (0.5, 2.0 * param, 2.0), "RRR": (param / 2.0, 2.0, 2.0),
-        "TLAMBDA": (1.0 / (1.0 + param), 1.0 + param, 1.0 + param),
-    }
-    return table[name]
+def algorithm_abc(name: str, param: float = 0.0):
+    """(a, b, c) the library uses for a named algorithm (pty_algorithm_abc)."""
+    L = load_library()
+    out = (ctypes.c_double * 3)()
+    _check(L.pty_algorithm_abc(ALGORITHMS[name.upper()], float(param), out), "pty_algorithm_abc")
+    return (out[0], out[1], out[2])
 
 
 class Scan:
@@ -260,6 +261,11 @@ class Scan:
     def synchronize(self):
         _check(self._L.pty_synchronize(self._h), "pty_synchronize")
 
+    def state_form(self) -> str:
+        """Exit-wave state the next iteration keeps: "x" or "w" (the blend
+        (1-a) x + a(1-b) y), as the library decides it (pty_state_form)."""
+        return "w" if self._L.pty_state_form(self._h) == 1 else "x"
+
     @property
     def iteration(self) -> int:
         return int(self._L.pty_get_iteration(self._h))
@@ -364,35 +370,5 @@ def workspace_bytes(n: int, n_pos: int, obj_h: int, obj_w: int, storage: str = "
     return int(L.pty_workspace_bytes(ctypes.byref(d)))
 
 
-def uses_blend_form(n: int, a: float, b: float, full_metrics: bool) -> bool:
-    """Whether the library keeps w = (1-a) x + a(1-b) y in place of x between
-    iterations (the same rule as the library: no full metrics, N <= 64, and
-    both coefficients non-zero in float32)."""
-    import numpy as np
-    return (not full_metrics and n <= 64 and np.float32(1.0 - a) != 0
-            and np.float32(a * (1.0 - b)) != 0)
-
-
-def algorithmic_bytes_per_projection(n: int, a: float, b: float, blind: bool = True,
-                                     storage: str = "fp32", full_metrics: bool = True) -> int:
-    """HBM bytes one diffraction pattern moves in one iteration (the roofline model).
-
-    divide: read x_{k-1} (if 1-a != 0 or metrics), y_{k-1} (if a(1-b) != 0 or
-    metrics), sqrt(I) (4 B); write x_k (same condition as its read), y_k.  In
-    the blend form: read w_{k-1} and sqrt(I), write w_k and y_k.
-    concur: read y_k once for the object, once more for the probe (blind).
-    """
-    e = 4 if storage == "fp16" else 8
-    nn = n * n
-    if uses_blend_form(n, a, b, full_metrics):
-        divide = e + 4 + e + e
-    else:
-        rx = e if (abs(1 - a) > 0 or full_metrics) else 0
-        ry = e if (abs(a * (1 - b)) > 0 or full_metrics) else 0
-        divide = rx + ry + 4 + rx + e
-    concur = e + (e if blind else 0)
-    return (divide + concur) * nn
-
-
-__all__ = ["Scan", "iterate_many", "load_library", "preset", "workspace_bytes", "PtyError",
-           "algorithmic_bytes_per_projection", "uses_blend_form", "EXPORTS", "LIB_PATH"]
+__all__ = ["Scan", "iterate_many", "load_library", "algorithm_abc", "workspace_bytes", "PtyError",
+           "EXPORTS", "LIB_PATH"]

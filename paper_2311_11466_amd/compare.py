@@ -15,7 +15,7 @@ from typing import Sequence
 
 import numpy as np
 
-from . import Scan, preset
+from . import Scan, algorithm_abc
 
 ALGORITHMS = (("DC", 0.0), ("AR", 0.0), ("DR", 0.0), ("SF", 0.0), ("RAAR", 0.75), ("RRR", 0.5),
               ("TLAMBDA", 0.5))
@@ -45,9 +45,9 @@ def error_lines(pos, intensity, obj0, probe0, truth, box, algorithms: Sequence =
             torch.as_tensor(np.asarray(probe0, np.complex64)).to(dev))
     out = {}
     for name, prm in algorithms:
-        abc = preset(name, prm)
+        abc = algorithm_abc(name, prm)
         g = Scan(*args, storage=storage, blind=True, device=dev, full_metrics=False)
-        g.set_algorithm(*abc)
+        g.set_algorithm_named(name, prm)
         g.set_concur_sweeps(sweeps)
         eo = []
         for _ in range(n_iter):
@@ -58,7 +58,7 @@ def error_lines(pos, intensity, obj0, probe0, truth, box, algorithms: Sequence =
         ms = None
         if timed:
             g = Scan(*args, storage=storage, blind=True, device=dev, full_metrics=False)
-            g.set_algorithm(*abc)
+            g.set_algorithm_named(name, prm)
             g.set_concur_sweeps(sweeps)
             g.iterate(5)
             g.synchronize()

@@ -264,6 +264,16 @@ DivideParams divide_params(const pty_scan* s) {
   return p;
 }
 
+// The divide over every pattern: one launch per stage (the N = 256 passes
+// each span all patterns).
+pty_status launch_divide(pty_scan* s, const DivideParams& p, bool timed_launch) {
+  for (int stage = 0; stage < divide_stages(s->N); ++stage) {
+    auto fn = [&] { return launch_divide_stage(s->N, s->fp16, p, s->J, stage, s->stream); };
+    PTY_HIP(s, timed_launch ? timed(s, PTY_K_DIVIDE + stage, fn) : fn(), "divide launch");
+  }
+  return PTY_OK;
+}
+
 // The concur of the y buffer into the scan's object and probe: s->sweeps
 // (object, probe) sweeps when the probe is updated, one object step
 // otherwise.  Every sweep's object launch writes the same metric slices and
@@ -319,7 +329,6 @@ bool use_blend(const pty_scan* s) {
 }
 
 pty_status launch_iteration(pty_scan* s) {
-  const hipStream_t st = s->stream;
   const bool wf = use_blend(s);
   if ((wf && s->mode == MODE_PENDING) || (!wf && s->mode == MODE_PENDING_W)) {
     // a change of form passes through a materialised x
@@ -354,10 +363,9 @@ pty_status launch_iteration(pty_scan* s) {
   p.write_x = write_x;
   p.c = float(s->c);
   if (s->prof && s->ev_class.size() > 4096) PTY_HIP(s, drain_profile(s), "profile drain");
-  for (int stage = 0; stage < divide_stages(s->N); ++stage) {
-    PTY_HIP(s, timed(s, PTY_K_DIVIDE + stage,
-                     [&] { return launch_divide_stage(s->N, s->fp16, p, s->J, stage, st); }),
-            "divide launch");
+  {
+    const pty_status ds = launch_divide(s, p, true);
+    if (ds != PTY_OK) return ds;
   }
 
   const bool update_probe = s->blind && s->k >= s->probe_update_start;
@@ -676,6 +684,23 @@ pty_status pty_set_algorithm_named(pty_scan* scan, int32_t algorithm, double par
   }
 }
 
+pty_status pty_algorithm_abc(int32_t algorithm, double param, double* abc) {
+  if (!abc) return fail(PTY_ERR_INVALID_ARG, "abc is NULL");
+  if (!std::isfinite(param)) return fail(PTY_ERR_INVALID_ARG, "param must be finite");
+  double a, b, c;
+  const pty_status st = named_abc(algorithm, param, &a, &b, &c);
+  if (st != PTY_OK) return st;
+  abc[0] = a;
+  abc[1] = b;
+  abc[2] = c;
+  return PTY_OK;
+}
+
+int32_t pty_state_form(const pty_scan* scan) {
+  if (!scan) return -1;
+  return use_blend(scan) ? 1 : 0;
+}
+
 pty_status pty_iterate(pty_scan* scan, int32_t n) {
   pty_status st = check_usable(scan);
   if (st != PTY_OK) return st;
@@ -765,8 +790,8 @@ pty_status pty_shadow(pty_scan* scan, float* obj_out, float* probe_out) {
     p.alpha = 0.f; p.beta = 0.f; p.gamma = 1.f;
     p.read_x = 1; p.read_y = 0; p.write_x = 1;
     p.c = 1.0f;
-    for (int stage = 0; stage < divide_stages(scan->N); ++stage)
-      PTY_HIP(scan, launch_divide_stage(scan->N, scan->fp16, p, scan->J, stage, s), "shadow divide");
+    st = launch_divide(scan, p, false);
+    if (st != PTY_OK) return st;
     scan->y_valid = false;
     // the consensus runs in place; the outputs first receive the current
     // (O, P) and are swapped with the result afterwards

@@ -22,7 +22,7 @@ from typing import Sequence
 
 import numpy as np
 
-from . import Scan, iterate_many, preset, workspace_bytes
+from . import Scan, iterate_many, workspace_bytes
 
 
 @dataclass
@@ -32,7 +32,8 @@ class Request:
     intensity: np.ndarray           # float32 [J, N, N]
     obj0: np.ndarray                # complex64 [H, W]
     probe0: np.ndarray              # complex64 [N, N]
-    abc: tuple                      # (a, b, c)
+    algorithm: str                  # a named algorithm of the library (DC, AR, DR, SF, RAAR, RRR, TLAMBDA)
+    param: float                    # its beta or lambda
     max_iter: int = 200
     tol: float = 1e-3               # completes once the Fourier error is below this
     arrival: float = 0.0            # seconds after the server starts
@@ -129,7 +130,7 @@ class Server:
                         torch.as_tensor(req.obj0).to(dev), torch.as_tensor(req.probe0).to(dev),
                         storage=req.storage, blind=True, device=dev, stream=stream,
                         full_metrics=False)   # completion reads the Fourier error only
-        scan.set_algorithm(*req.abc)
+        scan.set_algorithm_named(req.algorithm, req.param)
         return _Active(req, scan, stream, now, scan.workspace_bytes)
 
     def _finish(self, a: _Active, now: float, ef: float) -> Result:
@@ -202,7 +203,7 @@ def request_from_scan(rid: int, scan, algorithm: str, param: float, arrival: flo
     """Build a Request from a ptysynth Scan."""
     return Request(rid, scan.pos.astype(np.int32), scan.intensity.astype(np.float32),
                    scan.obj0.astype(np.complex64), scan.probe0.astype(np.complex64),
-                   preset(algorithm, param), max_iter, tol, arrival, storage)
+                   algorithm, float(param), max_iter, tol, arrival, storage)
 
 
 def poisson_arrivals(n: int, rate: float, seed: int = 501) -> np.ndarray:

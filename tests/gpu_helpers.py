@@ -66,3 +66,41 @@ def fp16_round(a, scale):
     re = (a.real.astype(np.float32) * np.float32(scale)).astype(np.float16).astype(np.float64) / scale
     im = (a.imag.astype(np.float32) * np.float32(scale)).astype(np.float16).astype(np.float64) / scale
     return re + 1j * im
+
+
+# Single-step parity gate (relative L2), the per-iteration tolerance of the
+# float32 path against the FP64 oracle from an identical state.
+STEP_GATE = 1e-5
+# relative size of the start perturbation used to measure the oracle's own
+# amplification of a difference
+PERTURB = 1e-7
+
+
+def trajectory_bound(drift, n_iter, gate=STEP_GATE, eps=PERTURB):
+    """Bound of a free-running GPU trajectory against the oracle's, per quantity.
+
+    Linearised error propagation: every GPU iteration differs from the
+    oracle's iteration from the same state by at most `gate` (relative; the
+    single-step gate), and the oracle itself turns a start difference of
+    relative size eps into `drift` after n_iter iterations, i.e. amplifies by
+    at most drift / eps (taken as at least 1).  Summing n_iter per-step
+    differences, each amplified at most that much, bounds the trajectory
+    difference by n_iter * gate * max(drift / eps, 1).  The bound says nothing
+    once it reaches order one (strongly amplifying iterations); the tests print
+    the measured difference next to it.
+    """
+    d = np.maximum(np.asarray(drift, dtype=np.float64), eps)
+    return n_iter * gate * d / eps
+
+
+def oracle_drift(run, base_x, compare, seeds=(1, 2), eps=PERTURB):
+    """Largest difference `compare(perturbed, reference)` between the oracle run
+    from base_x and from base_x perturbed by a relative eps (per seed)."""
+    ref = run(base_x)
+    worst = None
+    for sd in seeds:
+        rng = np.random.default_rng(sd)
+        b = run(base_x * (1 + eps * rng.standard_normal(base_x.shape)))
+        d = np.asarray(compare(b, ref), dtype=np.float64)
+        worst = d if worst is None else np.maximum(worst, d)
+    return ref, worst

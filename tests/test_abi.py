@@ -101,18 +101,38 @@ def test_positions_checked_before_device_work(lib):
     assert st == 1 and b"outside" in lib.pty_last_error()
 
 
+def test_named_algorithms_match_oracle_presets(lib):
+    """The library's (a, b, c) table (pty_algorithm_abc, a host-only call)
+    equals the oracle's presets, which the pins tie to each algorithm's
+    textbook update."""
+    from oracle import pty_oracle as po
+    for name, code in pk.ALGORITHMS.items():
+        for prm in (0.0, 0.3, 0.5, 0.75, 1.0):
+            out = (ctypes.c_double * 3)()
+            assert lib.pty_algorithm_abc(code, prm, out) == 0
+            assert tuple(out) == pytest.approx(po.preset(name, prm), rel=0, abs=1e-15), (name, prm)
+    out = (ctypes.c_double * 3)()
+    assert lib.pty_algorithm_abc(99, 0.5, out) == 1
+    assert lib.pty_algorithm_abc(0, float("nan"), out) == 1
+    assert lib.pty_algorithm_abc(0, 0.5, None) == 1
+    assert lib.pty_state_form(None) == -1
+
+
 def test_algorithmic_bytes_model():
-    # blind, general (a, b, c), float32: 52 bytes per pattern pixel
-    assert pk.algorithmic_bytes_per_projection(128, 0.5, 1.5) == 52 * 128 * 128
-    assert pk.algorithmic_bytes_per_projection(128, 0.5, 1.5, storage="fp16") == 28 * 128 * 128 + 4 * 0
-    assert pk.algorithmic_bytes_per_projection(64, 1, 1, full_metrics=False) == 28 * 64 * 64
-    assert pk.algorithmic_bytes_per_projection(64, 1, 1, blind=False, full_metrics=False) == 20 * 64 * 64
-    # blend form (no full metrics, N <= 64, a != 1, b != 1): w and sqrt(I) in,
-    # w and y out, then y twice: 44 bytes (float32), 24 (float16)
-    assert pk.algorithmic_bytes_per_projection(64, 0.5, 1.5, full_metrics=False) == 44 * 64 * 64
-    assert pk.algorithmic_bytes_per_projection(64, 0.5, 1.5, storage="fp16", full_metrics=False) == 24 * 64 * 64
-    # N = 128 and N = 256 keep x (split exchanges; three passes)
-    assert pk.algorithmic_bytes_per_projection(128, 0.5, 1.5, full_metrics=False) == 52 * 128 * 128
-    assert pk.algorithmic_bytes_per_projection(256, 0.5, 1.5, full_metrics=False) == 52 * 256 * 256
-    # SF (a = 1): the x form reads y only, 36 + 16 bytes
-    assert pk.algorithmic_bytes_per_projection(128, 1, 2, full_metrics=False) == 36 * 128 * 128
+    import bench
+    ab = bench.algorithmic_bytes
+
+    def per_px(n, abc, storage="fp32", full=True, form="x", blind=True):
+        return sum(ab(k, n, 1, abc, blind, storage, full, form) for k in ("divide", "object", "probe")) // (n * n)
+    raar, dc, sf = (0.5, 1.5, 2.0), (1, 1, 1), (1, 2, 1)
+    # blind, general (a, b, c), float32: 52 bytes per pattern pixel; the divide alone 36
+    assert per_px(128, raar) == 52 and ab("divide", 256, 1, raar, True, "fp32", True, "x") == 36 * 256 * 256
+    assert per_px(128, raar, "fp16") == 28
+    # a = b = 1 without full metrics: x is not kept, y and sqrt(I) only
+    assert per_px(64, dc, full=False) == 28
+    assert per_px(64, dc, full=False, blind=False) == 20
+    # blend form: w and sqrt(I) in, w and y out, then y twice: 44 (float32), 24 (float16)
+    assert per_px(64, raar, full=False, form="w") == 44
+    assert per_px(64, raar, "fp16", full=False, form="w") == 24
+    # SF (a = 1) in the x form reads y only: 36 + 16 bytes
+    assert per_px(128, sf, full=False) == 36

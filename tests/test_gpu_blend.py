@@ -14,7 +14,8 @@ import sys
 import numpy as np
 import pytest
 
-from gpu_helpers import amp32, covered_mask, gpu_scan, oracle_state_after, rel_l2, round_state, to_dev
+from gpu_helpers import (amp32, covered_mask, gpu_scan, oracle_state_after, rel_l2, round_state, to_dev,
+                         trajectory_bound, PERTURB)
 from oracle import pty_oracle as po
 from ptysynth import make_scan
 from ptysynth.scans import small_config
@@ -33,6 +34,10 @@ def get_scan(name):
             _SCANS[name] = make_scan("tiny_n32")
         elif name == "p64":
             _SCANS[name] = make_scan(small_config("p64", 64, 5, 24, jitter=2, photons=1e6, seed=31))
+        elif name == "p128":
+            _SCANS[name] = make_scan(small_config("p128", 128, 4, 40, jitter=2, photons=1e6, seed=41))
+        elif name == "p256":
+            _SCANS[name] = make_scan(small_config("p256", 256, 3, 80, jitter=3, photons=1e5, seed=51))
         else:
             raise KeyError(name)
     return _SCANS[name]
@@ -48,16 +53,18 @@ def blend_scan(scan, storage="fp32"):
 
 
 def test_blend_form_rule():
-    from paper_2311_11466_amd import uses_blend_form
-    for name, prm in BLEND:
-        a, b, _ = po.preset(name, prm)
-        assert uses_blend_form(32, a, b, False) and uses_blend_form(64, a, b, False)
-        assert not uses_blend_form(64, a, b, True)
-        assert not uses_blend_form(128, a, b, False)   # the x form's split exchanges are faster
-        assert not uses_blend_form(256, a, b, False)
-    for name in ("DC", "AR", "SF"):
-        a, b, _ = po.preset(name)
-        assert not uses_blend_form(32, a, b, False)
+    """The library keeps the blend w exactly when 1-a and a(1-b) are both
+    nonzero, without full metrics and for N <= 64 (pty_state_form)."""
+    for cfg in ("tiny_n32", "p64", "p128", "p256"):
+        scan = get_scan(cfg)
+        for full in (False, True):
+            g = gpu_scan(scan, full_metrics=full)
+            for name, prm in BLEND + [("DC", 0.0), ("AR", 0.0), ("SF", 0.0)]:
+                g.set_algorithm_named(name, prm)
+                a, b, _ = po.preset(name, prm)
+                want = (not full and scan.n <= 64 and np.float32(1 - a) != 0 and np.float32(a * (1 - b)) != 0)
+                assert g.state_form() == ("w" if want else "x"), (cfg, full, name)
+            g.close()
 
 
 def two_steps(scan, abc, storage="fp32", k_start=2):
@@ -156,7 +163,8 @@ def schedule_run(scan, schedule, x_scale=None):
 def test_blend_trajectory(cfg, schedule):
     """Free-running blend-form iterations, including switches of form between
     iterations (DC and SF run in the x form), against the oracle: bound 20 x
-    the oracle's drift under a 1e-7 perturbation of the start, at least 1e-5."""
+    the linearised trajectory bound (gate times the oracle's own amplification
+    of a 1e-7 perturbation of the start, per iteration)."""
     scan = get_scan(cfg)
     say("case: blend trajectory", cfg, [(a, n) for a, n in schedule])
     g = blend_scan(scan)
@@ -171,10 +179,10 @@ def test_blend_trajectory(cfg, schedule):
     worst = np.zeros(4)
     for sd in (1, 2, 3):
         rng = np.random.default_rng(sd)
-        pert, ef_p = schedule_run(scan, schedule, 1 + 1e-7 * rng.standard_normal(ref.x.shape))
+        pert, ef_p = schedule_run(scan, schedule, 1 + PERTURB * rng.standard_normal(ref.x.shape))
         worst = np.maximum(worst, [rel_l2(pert.x, ref.x), rel_l2(pert.obj, ref.obj, cov),
                                    rel_l2(pert.probe, ref.probe), float(np.max(np.abs(ef_p - ef_o) / ef_o))])
-    tol = np.maximum(20 * worst, 1e-5)
+    tol = trajectory_bound(worst, sum(n for _, n in schedule))
     errs = np.array([rel_l2(x, ref.x), rel_l2(o, ref.obj, cov), rel_l2(p, ref.probe),
                      float(np.max(np.abs(ef_g - ef_o) / ef_o))])
     say("  gpu-vs-oracle x/obj/probe/E_F", errs, "bound", tol)

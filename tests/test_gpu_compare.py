@@ -2,15 +2,16 @@
 
 The object error kernel against the oracle's aligned error on the same
 float32 arrays, and the harness's per-iteration Fourier and object error
-lines against the oracle's runs of the same presets (bound: 20 x the
-oracle's own drift under a 1e-7 start perturbation, floor 1e-5).
+lines against the oracle's runs of the same presets (the linearised
+trajectory bound: single-step gate times the oracle's own amplification of a
+1e-7 start perturbation, per iteration).
 """
 import sys
 
 import numpy as np
 import pytest
 
-from gpu_helpers import amp32, gpu_scan, rel_l2, to_dev
+from gpu_helpers import amp32, gpu_scan, rel_l2, to_dev, trajectory_bound
 from oracle import pty_oracle as po
 from ptysynth import comparison_config, make_scan
 
@@ -78,7 +79,7 @@ def test_error_lines_match_oracle(small_scan):
             rng = np.random.default_rng(sd)
             ef_p, eo_p = run(1 + 1e-7 * rng.standard_normal((scan.n_pos, scan.n, scan.n)))
             drift = np.maximum(drift, [np.max(np.abs(ef_p - ef_r) / ef_r), np.max(np.abs(eo_p - eo_r) / eo_r)])
-        tol = np.maximum(20 * drift, 1e-5)
+        tol = trajectory_bound(drift, n_iter)
         errs = np.array([np.max(np.abs(np.array(got["fourier_err"]) - ef_r) / ef_r),
                          np.max(np.abs(np.array(got["object_err"]) - eo_r) / eo_r)])
         say(f"  {lab}: E_F/E_O line errors", errs, "bound", tol)

@@ -15,7 +15,8 @@ import sys
 import numpy as np
 import pytest
 
-from gpu_helpers import amp32, covered_mask, gpu_scan, oracle_state_after, rel_l2, round_state, to_dev
+from gpu_helpers import (amp32, covered_mask, gpu_scan, oracle_state_after, rel_l2, round_state, to_dev,
+                         trajectory_bound, PERTURB)
 from oracle import pty_oracle as po
 from ptysynth import make_scan
 from ptysynth.scans import small_config
@@ -72,10 +73,10 @@ def test_fourier_only_two_steps(cfg, name, param):
     errs = {"y": rel_l2(y1, i1["y"]), "x": rel_l2(x2, s2.x), "obj": rel_l2(o2, s2.obj, cov),
             "probe": rel_l2(p2, s2.probe)}
     rng = np.random.default_rng(1)
-    q2, _, qi = two(st.x * (1 + 1e-7 * rng.standard_normal(st.x.shape)))
+    q2, _, qi = two(st.x * (1 + PERTURB * rng.standard_normal(st.x.shape)))
     drift = {"y": rel_l2(qi["y"], i1["y"]), "x": rel_l2(q2.x, s2.x), "obj": rel_l2(q2.obj, s2.obj, cov),
              "probe": rel_l2(q2.probe, s2.probe)}
-    tol = {k: max(TOL, 20 * v) for k, v in drift.items()}
+    tol = {k: float(trajectory_bound(v, 2)) for k, v in drift.items()}
     say("  errors", {k: f"{v:.2e}" for k, v in errs.items()}, "bounds", {k: f"{v:.2e}" for k, v in tol.items()})
     assert all(errs[k] <= tol[k] for k in errs), (errs, tol)
     assert np.array_equal(o2[~cov], s2.obj[~cov].astype(np.complex64))

@@ -3,8 +3,13 @@
 Gate: one iteration from an identical state (the oracle state rounded to
 float32 and loaded with set_state) must give x_{k+1}, y_k = P^c_D x_k, O_{k+1}
 and P_{k+1} within 1e-5 relative L2 of the oracle's iteration from the same
-rounded state.  Several iterations from the start are compared with a looser
-bound, since a non-convex iteration amplifies rounding differences.
+rounded state.  The gate is applied along the oracle's trajectory (k = 0, 1,
+10, 50, 100, 199), for every named algorithm set through the library's own
+table (pty_set_algorithm_named, compared with the oracle's presets), and to an
+iteration that starts from the library's pending update (the second of two
+uninterrupted iterations).  Free-running trajectories are compared with a
+bound derived from the gate and the oracle's own amplification of a
+difference.
 """
 import sys
 
@@ -12,19 +17,21 @@ import numpy as np
 import pytest
 
 from gpu_helpers import (rel_l2, gpu_scan, amp32, covered_mask, oracle_state_after, round_state,
-                         to_dev)
+                         to_dev, STEP_GATE, trajectory_bound, oracle_drift)
 from oracle import pty_oracle as po
 from ptysynth import make_scan
 from ptysynth.scans import small_config
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-5
+TOL = STEP_GATE
 PRESETS = [("DC", 0.0), ("AR", 0.0), ("DR", 0.0), ("SF", 0.0), ("RAAR", 0.75), ("RRR", 0.5),
            ("TLAMBDA", 0.5)]
 CUSTOM = [(0.3, 1.7, 0.6), (1.25, 0.5, 1.5)]
+SIZES = ["tiny_n32", "p64", "p128", "p256"]
 
 _SCANS = {}
+_TRAJ = {}
 
 
 def get_scan(name):
@@ -47,13 +54,44 @@ def say(*a):
     sys.stdout.flush()
 
 
-def single_step(scan, abc, blind=True, k_start=2, storage="fp32"):
-    """Run one GPU iteration and one oracle iteration from the same float32 state."""
-    st = round_state(oracle_state_after(scan, k_start, po.preset("RAAR", 0.75), blind=blind))
-    g = gpu_scan(scan, storage=storage, blind=blind)
+def oracle_state(scan_name, k, blind=True):
+    """The oracle's blind RAAR(0.75) state after k iterations from the scan's
+    start (cached per scan), rounded to float32."""
+    key = (scan_name, blind)
+    scan = get_scan(scan_name)
+    if key not in _TRAJ:
+        _TRAJ[key] = {0: po.init_state(scan.obj0, scan.probe0, scan.pos)}
+    traj = _TRAJ[key]
+    k0 = max(i for i in traj if i <= k)
+    st = traj[k0]
+    for i in range(k0, k):
+        st, _ = po.step(st, amp32(scan), scan.pos, *po.preset("RAAR", 0.75), blind=blind)
+        traj[i + 1] = st
+    return round_state(traj[k])
+
+
+def set_algo(g, algo):
+    """Select algo on the GPU scan: a named algorithm (name, param) through the
+    library's table, or an (a, b, c) triple.  Returns the oracle's (a, b, c)."""
+    if isinstance(algo[0], str):
+        g.set_algorithm_named(*algo)
+        return po.preset(*algo)
+    g.set_algorithm(*algo)
+    return tuple(algo)
+
+
+def load(g, st):
     g.set_state(to_dev(st.x.astype(np.complex64)), None, to_dev(st.obj.astype(np.complex64)),
                 to_dev(st.probe.astype(np.complex64)))
-    g.set_algorithm(*abc)
+
+
+def single_step(scan_name, algo, blind=True, k_start=2, storage="fp32", full_metrics=True):
+    """One GPU iteration and one oracle iteration from the same float32 state."""
+    scan = get_scan(scan_name)
+    st = oracle_state(scan_name, k_start, blind)
+    g = gpu_scan(scan, storage=storage, blind=blind, full_metrics=full_metrics)
+    load(g, st)
+    abc = set_algo(g, algo)
     g.iterate(1)
     x1, y0, o1, p1 = (t.cpu().numpy() for t in g.get_state())
     m = g.metrics(allow_diverged=True)
@@ -62,7 +100,7 @@ def single_step(scan, abc, blind=True, k_start=2, storage="fp32"):
     return (x1, y0, o1, p1, m), (new, info)
 
 
-def check_step(scan, got, ref, tol=TOL, what=""):
+def check_step(scan, got, ref, tol=TOL, what="", metrics=("fourier_err", "consistency_err", "change")):
     x1, y0, o1, p1, m = got
     new, info = ref
     cov = covered_mask(scan)
@@ -74,100 +112,120 @@ def check_step(scan, got, ref, tol=TOL, what=""):
     # pixels no window covers keep their value exactly
     assert np.array_equal(o1[~cov], new.obj[~cov].astype(np.complex64))
     om = info["metrics"]
-    for key in ("fourier_err", "consistency_err", "change"):
+    for key in metrics:
         assert abs(m[key] - om[key]) <= 1e-4 * abs(om[key]) + 1e-12, (what, key, m[key], om[key])
 
 
+@pytest.mark.parametrize("cfg", SIZES)
 @pytest.mark.parametrize("name,param", PRESETS)
-def test_single_step_presets_n32(name, param):
-    scan = get_scan("tiny_n32")
-    abc = po.preset(name, param)
-    say("case: single step tiny_n32", name, param)
-    got, ref = single_step(scan, abc)
-    check_step(scan, got, ref, what=f"n32 {name}")
+def test_single_step_named(cfg, name, param):
+    """Every named algorithm, selected through the library's table, against the
+    oracle's preset: an (a, b, c) table slip fails here."""
+    say("case: single step", cfg, name, param)
+    got, ref = single_step(cfg, (name, param))
+    check_step(get_scan(cfg), got, ref, what=f"{cfg} {name}")
 
 
 @pytest.mark.parametrize("abc", CUSTOM)
 def test_single_step_custom_abc(abc):
-    scan = get_scan("tiny_n32")
     say("case: single step tiny_n32 abc", abc)
-    got, ref = single_step(scan, abc)
-    check_step(scan, got, ref, what=f"n32 {abc}")
+    got, ref = single_step("tiny_n32", abc)
+    check_step(get_scan("tiny_n32"), got, ref, what=f"n32 {abc}")
 
 
-@pytest.mark.parametrize("cfg", ["p64", "p128", "p256"])
-@pytest.mark.parametrize("name,param", [("RAAR", 0.75), ("DC", 0.0), ("SF", 0.0)])
-def test_single_step_sizes(cfg, name, param):
-    scan = get_scan(cfg)
-    say("case: single step", cfg, name, param)
-    got, ref = single_step(scan, po.preset(name, param))
-    check_step(scan, got, ref, what=f"{cfg} {name}")
+@pytest.mark.parametrize("cfg,k", [("tiny_n32", k) for k in (0, 1, 10, 50, 100, 199)]
+                         + [("p128", k) for k in (0, 10, 50)] + [("p256", k) for k in (0, 10)])
+def test_single_step_along_trajectory(cfg, k):
+    """The gate at iterations along the oracle's blind RAAR(0.75) trajectory."""
+    say("case: single step along the trajectory", cfg, "k =", k)
+    got, ref = single_step(cfg, ("RAAR", 0.75), k_start=k)
+    check_step(get_scan(cfg), got, ref, what=f"{cfg} k={k}")
 
 
 @pytest.mark.parametrize("cfg", ["tiny_n32", "p128", "p256"])
 def test_single_step_known_probe(cfg):
-    scan = get_scan(cfg)
     say("case: known probe", cfg)
-    got, ref = single_step(scan, po.preset("DR"), blind=False)
-    check_step(scan, got, ref, what=f"{cfg} known")
+    got, ref = single_step(cfg, ("DR", 0.0), blind=False)
+    check_step(get_scan(cfg), got, ref, what=f"{cfg} known")
     assert np.array_equal(got[3], ref[0].probe.astype(np.complex64))
 
 
-def oracle_sensitivity(scan, abc, n_iter, seeds=(1, 2, 3), eps=1e-7):
-    """How far two oracle runs drift apart when the start differs by eps (relative).
+@pytest.mark.parametrize("full_metrics", [True, False])
+@pytest.mark.parametrize("cfg", SIZES)
+@pytest.mark.parametrize("name,param", PRESETS)
+def test_pending_step(cfg, name, param, full_metrics):
+    """The gate on an iteration that starts from the library's pending update.
 
-    A non-convex iteration amplifies differences; float32 rounding is such a
-    difference, so the GPU-vs-oracle bound of a free-running trajectory is
-    taken from the oracle's own amplification of a 1e-7 perturbation.
-    Returns per-quantity maxima over the seeds: x, obj (covered), probe, E_F.
-    """
-    amp = amp32(scan)
-    cov = covered_mask(scan)
-    base = po.init_state(scan.obj0.astype(np.complex64).astype(np.complex128),
-                         scan.probe0.astype(np.complex64).astype(np.complex128), scan.pos)
-    ref = po.run(base.copy(), amp, scan.pos, *abc, n_iter, blind=True)
-    worst = np.zeros(4)
-    for sd in seeds:
-        rng = np.random.default_rng(sd)
-        b = base.copy()
-        b.x = b.x * (1 + eps * rng.standard_normal(b.x.shape))
-        b = po.run(b, amp, scan.pos, *abc, n_iter, blind=True)
-        ef_a = np.array([m["fourier_err"] for m in ref.history])
-        ef_b = np.array([m["fourier_err"] for m in b.history])
-        d = [rel_l2(b.x, ref.x), rel_l2(b.obj, ref.obj, cov), rel_l2(b.probe, ref.probe),
-             float(np.max(np.abs(ef_a - ef_b) / ef_a))]
-        worst = np.maximum(worst, d)
-    return ref, worst
-
-
-@pytest.mark.parametrize("cfg,abc,n_iter", [
-    ("tiny_n32", po.preset("RAAR", 0.75), 20),
-    ("tiny_n32", po.preset("DC"), 20),
-    ("p64", po.preset("RRR", 0.5), 10),
-    ("p256", po.preset("DR"), 5),
-])
-def test_trajectory(cfg, abc, n_iter):
-    """Free-running iterations from the start: state and Fourier-error history.
-
-    Bound: 20 x the oracle's own drift under a 1e-7 start perturbation, and
-    never looser than needed: at least 1e-5.
-    """
+    The second of two uninterrupted iterations forms x_{k+1} in its prologue
+    from the first iteration's (a b, a(1-b), 1-a) (or from the stored blend w);
+    a twin scan runs the first iteration alone and reads its state back (the
+    library materialises x with the prologue's arithmetic and is bitwise
+    deterministic), and the oracle's iteration from that state is compared
+    with the second iteration at 1e-5."""
     scan = get_scan(cfg)
-    say("case: trajectory", cfg, abc, n_iter)
+    say("case: pending step", cfg, name, param, "full metrics" if full_metrics else "fourier only")
+    st = oracle_state(cfg, 2)
+    a = gpu_scan(scan, full_metrics=full_metrics)
+    load(a, st)
+    abc = set_algo(a, (name, param))
+    form = a.state_form()
+    a.iterate(1)
+    x1, _, o1, p1 = (t.cpu().numpy() for t in a.get_state())
+    a.close()
+    b = gpu_scan(scan, full_metrics=full_metrics)
+    load(b, st)
+    set_algo(b, (name, param))
+    b.iterate(2)
+    x2, y1, o2, p2 = (t.cpu().numpy() for t in b.get_state())
+    hist = b.metric_history()
+    b.close()
+    s1 = po.State(x1.astype(np.complex128), o1.astype(np.complex128), p1.astype(np.complex128), 1)
+    new, info = po.step(s1, amp32(scan), scan.pos, *abc, blind=True)
+    metrics = ("fourier_err", "consistency_err", "change") if full_metrics else ("fourier_err",)
+    check_step(scan, (x2, y1, o2, p2, hist[-1]), (new, info), what=f"{cfg} {name} pending ({form} form)",
+               metrics=metrics)
+    assert hist[-1]["iteration"] == 1
+
+
+@pytest.mark.parametrize("cfg,algo,n_iter", [
+    ("tiny_n32", ("RAAR", 0.75), 20),
+    ("tiny_n32", ("DC", 0.0), 20),
+    ("p64", ("RRR", 0.5), 10),
+    ("p256", ("DR", 0.0), 5),
+])
+def test_trajectory(cfg, algo, n_iter):
+    """Free-running iterations from the start: state and Fourier-error history,
+    within the linearised bound n_iter * gate * (oracle amplification)."""
+    scan = get_scan(cfg)
+    say("case: trajectory", cfg, algo, n_iter)
     g = gpu_scan(scan)
-    g.set_algorithm(*abc)
+    abc = set_algo(g, algo)
     g.iterate(n_iter)
     x, y, o, p = (t.cpu().numpy() for t in g.get_state())
     hist = g.metric_history()
     g.close()
-    ref, sens = oracle_sensitivity(scan, abc, n_iter)
-    tol = np.maximum(20 * sens, 1e-5)
+    amp = amp32(scan)
     cov = covered_mask(scan)
+    base = po.init_state(scan.obj0.astype(np.complex64).astype(np.complex128),
+                         scan.probe0.astype(np.complex64).astype(np.complex128), scan.pos)
+
+    def run(x0):
+        b = base.copy()
+        b.x = x0
+        return po.run(b, amp, scan.pos, *abc, n_iter, blind=True)
+
+    def diff(b, r):
+        ef_a = np.array([m["fourier_err"] for m in r.history])
+        ef_b = np.array([m["fourier_err"] for m in b.history])
+        return [rel_l2(b.x, r.x), rel_l2(b.obj, r.obj, cov), rel_l2(b.probe, r.probe),
+                float(np.max(np.abs(ef_a - ef_b) / ef_a))]
+    ref, drift = oracle_drift(run, base.x, diff)
+    tol = trajectory_bound(drift, n_iter)
     ef_g = np.array([m["fourier_err"] for m in hist])
     ef_o = np.array([m["fourier_err"] for m in ref.history])
     errs = np.array([rel_l2(x, ref.x), rel_l2(o, ref.obj, cov), rel_l2(p, ref.probe),
                      float(np.max(np.abs(ef_g - ef_o) / ef_o))])
-    say("  gpu-vs-oracle x/obj/probe/E_F", errs, "oracle drift", sens)
+    say("  gpu-vs-oracle x/obj/probe/E_F", errs, "oracle drift", drift, "bound", tol)
     assert np.all(errs <= tol), (errs, tol)
     assert [m["iteration"] for m in hist] == list(range(n_iter))
 
@@ -282,7 +340,7 @@ def test_edge_zero_wave_and_zero_data(cfg):
         pass
     s = S()
     s.pos, s.intensity, s.obj0, s.probe0 = scan.pos, inten, scan.obj0, scan.probe0
-    st = round_state(oracle_state_after(scan, 1, po.preset("DC")))
+    st = oracle_state(cfg, 1)
     st.x[3] = 0.0
     g = gpu_scan(s)
     g.set_state(to_dev(st.x.astype(np.complex64)), None, to_dev(st.obj.astype(np.complex64)),
@@ -333,7 +391,10 @@ def test_fp16_storage_single_step(cfg):
 def test_c1_known_probe_then_blind_dc():
     """The 32-pixel scan's reference run: DC with the probe held for 50
     iterations, then blind, 200 iterations in all (probe_update_start = 50),
-    against the oracle's same run; bound from the oracle's own drift."""
+    against the oracle's same run, within the linearised trajectory bound.
+    (The scan description both holds the probe for 50 iterations and starts
+    it from a disc of radius 8; the reading taken here holds that start probe
+    for 50 iterations.)"""
     scan = get_scan("tiny_n32")
     abc = po.preset("DC")
     n_iter, start = 200, 50
@@ -362,7 +423,7 @@ def test_c1_known_probe_then_blind_dc():
         ef_b = np.array([m["fourier_err"] for m in b.history])
         worst = np.maximum(worst, [rel_l2(b.x, ref.x), rel_l2(b.obj, ref.obj, cov), rel_l2(b.probe, ref.probe),
                                    float(np.max(np.abs(ef_b - ef_r) / ef_r))])
-    tol = np.maximum(20 * worst, 1e-5)
+    tol = trajectory_bound(worst, n_iter)
     errs = np.array([rel_l2(x, ref.x), rel_l2(o, ref.obj, cov), rel_l2(p, ref.probe),
                      float(np.max(np.abs(ef_g - ef_r) / ef_r))])
     say("  gpu-vs-oracle x/obj/probe/E_F", errs, "bound", tol)

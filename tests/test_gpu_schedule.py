@@ -1,15 +1,17 @@
 """GPU parity of iteration-dependent relaxation, K concur sweeps and the shadow estimate.
 
 Gates as for the plain iteration: one step from an identical float32 state
-within 1e-5 of the oracle; free-running runs within 20 x the oracle's own
-drift under a 1e-7 perturbation of the start (floor 1e-5).
+within 1e-5 of the oracle; free-running runs within the linearised
+trajectory bound (the gate times the oracle's own amplification of a 1e-7
+perturbation of the start, per iteration).
 """
 import sys
 
 import numpy as np
 import pytest
 
-from gpu_helpers import amp32, covered_mask, gpu_scan, oracle_state_after, rel_l2, round_state, to_dev
+from gpu_helpers import (amp32, covered_mask, gpu_scan, oracle_state_after, rel_l2, round_state, to_dev,
+                         trajectory_bound, PERTURB)
 from oracle import pty_oracle as po
 from ptysynth import make_scan
 from ptysynth.scans import small_config
@@ -47,8 +49,9 @@ SCHEDULE = ([po.preset("RAAR", 0.75)] * 3 + [po.preset("DC")] * 2 + lambda_sched
             + [po.preset("RRR", 0.5)] * 2 + [(0.8, 1.3, 0.9)])
 
 
-def oracle_drift_bound(scan, run, n_seeds=3, eps=1e-7):
-    """Reference run and 20 x its drift under a 1e-7 start perturbation (floor 1e-5)."""
+def oracle_drift_bound(scan, run, n_iter, n_seeds=3, eps=PERTURB):
+    """Reference run and the linearised trajectory bound over n_iter
+    iterations from its drift under a 1e-7 start perturbation."""
     amp = amp32(scan)
     cov = covered_mask(scan)
     base = po.init_state(scan.obj0.astype(np.complex64).astype(np.complex128),
@@ -64,7 +67,7 @@ def oracle_drift_bound(scan, run, n_seeds=3, eps=1e-7):
         ef_b = np.array([m["fourier_err"] for m in b.history])
         worst = np.maximum(worst, [rel_l2(b.x, ref.x), rel_l2(b.obj, ref.obj, cov), rel_l2(b.probe, ref.probe),
                                    float(np.max(np.abs(ef_b - ef_r) / ef_r))])
-    return ref, np.maximum(20 * worst, 1e-5)
+    return ref, trajectory_bound(worst, n_iter, eps=eps)
 
 
 def compare_run(scan, g, ref, tol, what):
@@ -83,7 +86,7 @@ def test_schedule_trajectory():
     g = gpu_scan(scan)
     g.iterate_schedule(SCHEDULE)
     assert g.iteration == len(SCHEDULE)
-    ref, tol = oracle_drift_bound(scan, lambda st, amp: po.run_schedule(st, amp, scan.pos, SCHEDULE))
+    ref, tol = oracle_drift_bound(scan, lambda st, amp: po.run_schedule(st, amp, scan.pos, SCHEDULE), len(SCHEDULE))
     compare_run(scan, g, ref, tol, "schedule")
     g.close()
 
@@ -140,17 +143,17 @@ def test_concur_sweeps_single_step(cfg):
     errs = {"y": rel_l2(y0, info["y"]), "x": rel_l2(x1, new.x), "obj": rel_l2(o1, new.obj, cov),
             "probe": rel_l2(p1, new.probe)}
     # each sweep divides by the overlap sums again, so weakly lit object pixels
-    # amplify float32 rounding; bound: 20 x the oracle's own drift under a 1e-7
-    # perturbation of the state (at least 1e-5)
+    # amplify float32 rounding; bound: the gate times the oracle's own
+    # amplification of a 1e-7 perturbation of the state (one iteration)
     drift = {k: 0.0 for k in errs}
     for sd in (1, 2):
         rng = np.random.default_rng(sd)
-        pst = po.State(st.x * (1 + 1e-7 * rng.standard_normal(st.x.shape)), st.obj, st.probe, st.k)
+        pst = po.State(st.x * (1 + PERTURB * rng.standard_normal(st.x.shape)), st.obj, st.probe, st.k)
         pn, pi = po.step(pst, amp32(scan), scan.pos, *abc, sweeps=3)
         d = {"y": rel_l2(pi["y"], info["y"]), "x": rel_l2(pn.x, new.x), "obj": rel_l2(pn.obj, new.obj, cov),
              "probe": rel_l2(pn.probe, new.probe)}
         drift = {k: max(drift[k], d[k]) for k in d}
-    tol = {k: max(TOL, 20 * drift[k]) for k in errs}
+    tol = {k: float(trajectory_bound(drift[k], 1)) for k in errs}
     say("  errors", {k: f"{v:.2e}" for k, v in errs.items()}, "bounds", {k: f"{v:.2e}" for k, v in tol.items()})
     assert all(errs[k] <= tol[k] for k in errs), (errs, tol)
     # three sweeps differ from one (the consensus moved further)
@@ -166,7 +169,7 @@ def test_concur_sweeps_trajectory():
     g.set_algorithm(*abc)
     g.set_concur_sweeps(2)
     g.iterate(10)
-    ref, tol = oracle_drift_bound(scan, lambda st, amp: po.run(st, amp, scan.pos, *abc, 10, sweeps=2))
+    ref, tol = oracle_drift_bound(scan, lambda st, amp: po.run(st, amp, scan.pos, *abc, 10, sweeps=2), 10)
     compare_run(scan, g, ref, tol, "sweeps")
     g.close()
 

@@ -1,39 +1,94 @@
 """GPU tests of the served form: continuous batching gives every request the
-result it gets alone, admission respects the HBM budget and the slots."""
+result it gets alone (bitwise), every result agrees with the FP64 oracle,
+admission respects the HBM budget and the slots, and a request completes once
+its Fourier error is below its tolerance.
+
+Requests span the pattern sizes of the served mixed load (N = 64, 128, 256)
+with few positions, so the oracle reruns each of them in seconds.  A request
+of one iteration is held to the single-step gate (1e-5) from its float32
+start; a longer one to the linearised trajectory bound.
+"""
 import numpy as np
 import pytest
 
+from gpu_helpers import rel_l2, PERTURB, STEP_GATE, trajectory_bound
+from oracle import pty_oracle as po
 from ptysynth import make_scan
 from ptysynth.scans import small_config
 
 pytestmark = pytest.mark.gpu
 
+# (n, raster, step, algorithm, param, arrival, max_iter, noise-free start from the truth)
+SPECS = [
+    (64, 3, 24, "RAAR", 0.75, 0.0, 20, False),
+    (128, 3, 40, "DR", 0.0, 0.0, 20, False),
+    (256, 2, 80, "RRR", 0.5, 0.0, 10, False),
+    (64, 3, 24, "DC", 0.0, 0.01, 30, True),     # completes by tolerance at its first check
+    (128, 2, 40, "SF", 0.0, 0.02, 1, False),    # one iteration: single-step gate
+    (256, 2, 80, "AR", 0.0, 0.03, 1, False),
+    (64, 2, 24, "TLAMBDA", 0.5, 0.04, 1, False),
+]
+TOL_EF = 1e-6
+_CACHE = {}
+
+
+def _scans():
+    if "scans" not in _CACHE:
+        out = []
+        for i, (n, ras, step, algo, prm, t, it, truth) in enumerate(SPECS):
+            cfg = small_config(f"r{i}", n, ras, step, jitter=1, photons=None if truth else 1e5, seed=70 + 3 * i)
+            out.append(make_scan(cfg))
+        _CACHE["scans"] = out
+    return _CACHE["scans"]
+
 
 def _requests():
     from paper_2311_11466_amd.serve import request_from_scan
-    specs = [  # (n, raster, step, algorithm, param, arrival)
-        (32, 4, 12, "RAAR", 0.75, 0.0),
-        (64, 3, 24, "DR", 0.0, 0.0),
-        (32, 5, 10, "RRR", 0.5, 0.0),
-        (64, 4, 20, "DC", 0.0, 0.02),
-        (32, 3, 12, "SF", 0.0, 0.04),
-        (64, 3, 28, "AR", 0.0, 0.05),
-    ]
     reqs = []
-    for i, (n, ras, step, algo, prm, t) in enumerate(specs):
-        sc = make_scan(small_config(f"r{i}", n, ras, step, jitter=1, photons=1e5, seed=70 + 3 * i))
-        reqs.append(request_from_scan(i, sc, algo, prm, arrival=t, max_iter=30, tol=1e-9))
+    for i, (sc, spec) in enumerate(zip(_scans(), SPECS)):
+        n, ras, step, algo, prm, t, it, truth = spec
+        r = request_from_scan(i, sc, algo, prm, arrival=t, max_iter=it, tol=TOL_EF if truth else 1e-12)
+        if truth:
+            r.obj0 = sc.obj_true.astype(np.complex64)
+            r.probe0 = sc.probe_true.astype(np.complex64)
+        reqs.append(r)
     return reqs
 
 
-def test_mix_equals_alone_bitwise():
+def _oracle(req, n_iter, eps=0.0, seed=0):
+    """The oracle's run of a request from its float32 start (optionally with the
+    exit waves perturbed by a relative eps)."""
+    amp = np.sqrt(req.intensity.astype(np.float32).astype(np.float64))
+    st = po.init_state(req.obj0.astype(np.complex128), req.probe0.astype(np.complex128), req.pos)
+    if eps:
+        rng = np.random.default_rng(seed)
+        st.x = st.x * (1 + eps * rng.standard_normal(st.x.shape))
+    return po.run(st, amp, req.pos, *po.preset(req.algorithm, req.param), n_iter, blind=True)
+
+
+def _covered(req):
+    m = np.zeros(req.obj0.shape, bool)
+    for p, q in req.pos:
+        m[p:p + req.n, q:q + req.n] = True
+    return m
+
+
+@pytest.fixture(scope="module")
+def served():
     from paper_2311_11466_amd.serve import Server
     reqs = _requests()
-    print("case: served mix of", len(reqs), "requests", flush=True)
+    print("case: served mix of", len(reqs), "requests, N =", [r.n for r in reqs], flush=True)
     mix = Server(max_slots=3, chunk=10).run(reqs)
+    return reqs, mix
+
+
+def test_mix_equals_alone_bitwise(served):
+    from paper_2311_11466_amd.serve import Server
+    reqs, mix = served
     assert len(mix.results) == len(reqs)
     assert mix.peak_active <= 3
     for r in reqs:
+        print("  alone", r.rid, flush=True)
         alone = Server(max_slots=1, chunk=10).run([r]).results[0]
         got = mix.results[r.rid]
         assert got.iterations == alone.iterations
@@ -41,6 +96,37 @@ def test_mix_equals_alone_bitwise():
         assert np.array_equal(got.probe.view(np.uint32), alone.probe.view(np.uint32)), r.rid
     s = mix.summary()
     assert s["p99_latency_s"] >= s["p50_latency_s"] > 0 and s["projections_per_s"] > 0
+
+
+def test_served_results_match_oracle(served):
+    reqs, mix = served
+    for r in reqs:
+        got = mix.results[r.rid]
+        truth_start = SPECS[r.rid][7]
+        if truth_start:
+            # noise-free data from the true state: E_F is at rounding level, so
+            # the request completes at its first check, before its limit
+            assert got.iterations == 10 < r.max_iter, got.iterations
+            assert got.fourier_err < TOL_EF
+        else:
+            assert got.iterations == r.max_iter
+        ref = _oracle(r, got.iterations)
+        cov = _covered(r)
+        errs = np.array([rel_l2(got.obj, ref.obj, cov), rel_l2(got.probe, ref.probe)])
+        if got.iterations == 1:
+            bound = np.array([STEP_GATE, STEP_GATE])
+        else:
+            drift = np.zeros(2)
+            for sd in (1, 2):
+                q = _oracle(r, got.iterations, PERTURB, sd)
+                drift = np.maximum(drift, [rel_l2(q.obj, ref.obj, cov), rel_l2(q.probe, ref.probe)])
+            bound = trajectory_bound(drift, got.iterations)
+        ef_o = ref.history[-1]["fourier_err"]
+        print(f"  request {r.rid} N={r.n} {r.algorithm} {got.iterations} it: obj/probe {errs} bound {bound}; "
+              f"E_F gpu {got.fourier_err:.4e} oracle {ef_o:.4e}", flush=True)
+        assert np.all(errs <= bound), (r.rid, errs, bound)
+        if got.iterations == 1:
+            assert abs(got.fourier_err - ef_o) <= 1e-4 * ef_o, (r.rid, got.fourier_err, ef_o)
 
 
 def test_admission_by_budget():
@@ -65,7 +151,7 @@ def test_iterate_many_matches_iterate():
         with torch.cuda.stream(stream):
             g = pk.Scan(torch.as_tensor(r.pos).to(dev), torch.as_tensor(r.intensity).to(dev),
                         torch.as_tensor(r.obj0).to(dev), torch.as_tensor(r.probe0).to(dev), stream=stream)
-        g.set_algorithm(*r.abc)
+        g.set_algorithm_named(r.algorithm, r.param)
         return g
     streams = [torch.cuda.Stream() for _ in reqs]
     many = [mk(r, s) for r, s in zip(reqs, streams)]
