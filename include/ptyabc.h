@@ -224,6 +224,24 @@ int32_t pty_sp_last_batches(const pty_scan *scan);
 pty_status pty_object_error(pty_scan *scan, const float *truth, int32_t r0, int32_t c0, int32_t h, int32_t w,
                             double *err);
 
+/* The object error above without a scan, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops that forbid
+ * allocation): min over complex g of sum |t - g o|^2 / sum |t|^2 over the box
+ * rows [r0, r0+h), columns [c0, c0+w) of obj ([obj_h][obj_w] complex,
+ * row-major, device memory) against truth ([h][w] complex, device memory).
+ * The result (NaN for an all-zero truth, 1 for an all-zero object box) is
+ * written to err, a device double, asynchronously on stream (a hipStream_t;
+ * NULL: the default stream); nothing is synchronised.  The float64 partial
+ * sums live in a static device array of the library (32 KiB per GPU, kept
+ * until the process ends), not in allocated memory: the box may hold at most
+ * 16777216 (4096^2) pixels, larger boxes are rejected with
+ * PTY_ERR_INVALID_ARG before any device work.  All calls on one GPU share that
+ * array, so calls that overlap on one GPU (other streams, other threads)
+ * race.  Same kernels and summation order as pty_object_error, so the two
+ * give bitwise-equal results.  Calls no allocating routine. */
+pty_status pty_object_error_noalloc(const float *obj, int32_t obj_h, int32_t obj_w, const float *truth,
+                                    int32_t r0, int32_t c0, int32_t h, int32_t w, double *err, void *stream);
+
 /* Wait for all queued work of the scan. */
 pty_status pty_synchronize(pty_scan *scan);
 

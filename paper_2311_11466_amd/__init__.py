@@ -33,6 +33,7 @@ EXPORTS = [
     "pty_set_state", "pty_destroy_scan", "pty_status_string", "pty_last_error",
     "pty_profile", "pty_profile_read", "pty_iterate_schedule", "pty_set_concur_sweeps", "pty_shadow",
     "pty_object_error", "pty_sp_iterate", "pty_sp_last_batches", "pty_algorithm_abc", "pty_state_form",
+    "pty_object_error_noalloc",
 ]
 KERNEL_CLASSES = ["divide", "divide_cols", "divide_rows_inv", "object", "probe", "final"]
 
@@ -109,6 +110,8 @@ def load_library(path: str = LIB_PATH):
     L.pty_sp_iterate.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_double]
     L.pty_algorithm_abc.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    L.pty_object_error_noalloc.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_int32, P, P]
     L.pty_state_form.argtypes = [P]
     L.pty_state_form.restype = ctypes.c_int32
     L.pty_sp_last_batches.argtypes = [P]
@@ -119,7 +122,7 @@ def load_library(path: str = LIB_PATH):
                  "pty_iterate_many", "pty_synchronize", "pty_get_object", "pty_get_probe",
                  "pty_get_metrics", "pty_get_metric_history", "pty_get_state", "pty_set_state",
                  "pty_iterate_schedule", "pty_set_concur_sweeps", "pty_shadow", "pty_object_error", "pty_sp_iterate",
-                 "pty_algorithm_abc"):
+                 "pty_algorithm_abc", "pty_object_error_noalloc"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L

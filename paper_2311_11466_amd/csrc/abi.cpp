@@ -32,7 +32,6 @@ constexpr int kTileW = 64, kTileH = 16;
 constexpr int kDefaultCap = 4096;
 constexpr double kDefaultTau = 1e-10;
 constexpr int kMaxSweeps = 64;
-constexpr int kEvalBlocks = 64;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -112,7 +111,7 @@ Layout make_layout(const pty_scan_desc* d) {
   L.pmax = take(size_t(L.npb) * 4);
   L.tw = take(N * 8);
   L.flag = take(64);
-  L.eval = take(size_t(kEvalBlocks + 1) * 4 * 8);   // object-error partial sums and result
+  L.eval = take(size_t(object_error_blocks((long long)H * W) + 1) * 4 * 8);   // object-error partial sums, result
   L.sp_list = take(J * 4);                            // batch member lists of sequential projections
   L.total = off;
   return L;
@@ -933,16 +932,40 @@ pty_status pty_object_error(pty_scan* scan, const float* truth, int32_t r0, int3
     if (h < 1 || w < 1 || r0 < 0 || c0 < 0 || r0 + h > scan->H || c0 + w > scan->W)
       return fail(PTY_ERR_INVALID_ARG, "the box must lie inside the object");
     double* part = scan->at<double>(scan->L.eval);
+    const int blocks = object_error_blocks((long long)h * w);
     PTY_HIP(scan, launch_object_error(scan->at<float2>(scan->L.obj), scan->W, reinterpret_cast<const float2*>(truth),
-                                      r0, c0, h, w, part, kEvalBlocks, scan->stream),
+                                      r0, c0, h, w, part, blocks, part + 4 * blocks, scan->stream),
             "object error");
     double out = 0.0;
-    PTY_HIP(scan, hipMemcpyAsync(&out, part + 4 * kEvalBlocks, 8, hipMemcpyDeviceToHost, scan->stream), "copy");
+    PTY_HIP(scan, hipMemcpyAsync(&out, part + 4 * blocks, 8, hipMemcpyDeviceToHost, scan->stream), "copy");
     PTY_HIP(scan, hipStreamSynchronize(scan->stream), "synchronize");
     *err = out;
     return PTY_OK;
   } catch (const std::bad_alloc&) {
     return fail(PTY_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PTY_ERR_DEVICE, "unexpected exception");
+  }
+}
+
+pty_status pty_object_error_noalloc(const float* obj, int32_t obj_h, int32_t obj_w, const float* truth, int32_t r0,
+                                    int32_t c0, int32_t h, int32_t w, double* err, void* stream) {
+  try {
+    if (!obj || !truth || !err) return fail(PTY_ERR_INVALID_ARG, "obj, truth and err must be device pointers");
+    if (obj_h < 1 || obj_w < 1 || int64_t(obj_h) * obj_w > (int64_t(1) << 31))
+      return fail(PTY_ERR_INVALID_ARG, "object size out of range");
+    if (h < 1 || w < 1 || r0 < 0 || c0 < 0 || int64_t(r0) + h > obj_h || int64_t(c0) + w > obj_w)
+      return fail(PTY_ERR_INVALID_ARG, "the box must lie inside the object");
+    const long long pixels = (long long)h * w;
+    if (object_error_blocks(pixels) > kErrScratchBlocks)
+      return fail(PTY_ERR_INVALID_ARG, "box of " + std::to_string(pixels) + " pixels exceeds the static scratch of " +
+                                           std::to_string((long long)kErrScratchBlocks * kErrPixelsPerBlock) +
+                                           " pixels");
+    const hipError_t e = object_error_static(reinterpret_cast<const float2*>(obj), obj_w,
+                                             reinterpret_cast<const float2*>(truth), r0, c0, h, w, err,
+                                             reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_fail(nullptr, e, "object error (static scratch)");
+    return PTY_OK;
   } catch (...) {
     return fail(PTY_ERR_DEVICE, "unexpected exception");
   }

@@ -16,6 +16,7 @@
 // sums slices of the metric partials, which the finalise kernel's last block
 // adds up.
 #include <algorithm>
+#include <mutex>
 
 #include "common.hpp"
 #include "params.hpp"
@@ -514,23 +515,59 @@ __global__ __launch_bounds__(256) void object_error_part_kernel(const float2* __
   if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = acc[threadIdx.x];
 }
 
-__global__ void object_error_finish_kernel(double* part, int blocks) {
+__global__ void object_error_finish_kernel(const double* part, int blocks, double* result) {
   if (threadIdx.x != 0) return;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = 0; b < blocks; ++b)
     for (int q = 0; q < 4; ++q) s[q] += part[b * 4 + q];
   double e = __builtin_nan("");
   if (s[0] > 0.0) e = s[1] > 0.0 ? (s[0] - (s[2] * s[2] + s[3] * s[3]) / s[1]) / s[0] : 1.0;
-  part[blocks * 4] = e;
+  *result = e;
 }
 
 hipError_t launch_object_error(const float2* o, int ow, const float2* t, int r0, int c0, int h, int w, double* part,
-                               int blocks, hipStream_t s) {
+                               int blocks, double* result, hipStream_t s) {
   hipLaunchKernelGGL(object_error_part_kernel, dim3(blocks), dim3(256), 0, s, o, ow, t, r0, c0, h, w, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(object_error_finish_kernel, dim3(1), dim3(64), 0, s, part, blocks);
+  hipLaunchKernelGGL(object_error_finish_kernel, dim3(1), dim3(64), 0, s, part, blocks, result);
   return hipGetLastError();
+}
+
+// Partial sums of the allocation-free object error: every work-group writes
+// its four sums before the finishing kernel reads them, so nothing needs
+// clearing; all calls on one GPU share this array, so calls that overlap on
+// that GPU (different streams, or threads) race.
+static __device__ __align__(256) double scratch[4 * kErrScratchBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {};   // each device's address of `scratch`, looked up once
+}  // namespace
+
+hipError_t object_error_static(const float2* o, int ow, const float2* t, int r0, int c0, int h, int w,
+                               double* result, hipStream_t s) {
+  const int blocks = object_error_blocks((long long)h * w);
+  if (blocks > kErrScratchBlocks) return hipErrorInvalidValue;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[dev]) {
+      // with this device current: the array's address on this device
+      e = hipGetSymbolAddress(&g_scratch_addr[dev], HIP_SYMBOL(scratch));
+      if (e != hipSuccess) {
+        g_scratch_addr[dev] = nullptr;
+        return e;
+      }
+    }
+    ptr = g_scratch_addr[dev];
+  }
+  return launch_object_error(o, ow, t, r0, c0, h, w, static_cast<double*>(ptr), blocks, result, s);
 }
 
 hipError_t launch_metric_slices(const MetricParams& p, hipStream_t s) {

@@ -158,10 +158,21 @@ hipError_t launch_sp_n64(const DivideParams& p, int count, hipStream_t s);
 hipError_t launch_sp_n128(const DivideParams& p, int count, hipStream_t s);
 hipError_t launch_sp_probe(const SpProbeParams& p, hipStream_t s);
 // min over complex g of sum |t - g o|^2 / sum |t|^2 over the box [r0, r0+h) x [c0, c0+w)
-// of o (row pitch ow) against t ([h][w]); part holds 4 (blocks + 1) doubles, the
-// result lands in part[4 blocks]
+// of o (row pitch ow) against t ([h][w]); part holds 4 blocks doubles (one set of
+// float64 partial sums per work-group), the result lands in *result
 hipError_t launch_object_error(const float2* o, int ow, const float2* t, int r0, int c0, int h, int w, double* part,
-                               int blocks, hipStream_t s);
+                               int blocks, double* result, hipStream_t s);
+// work-groups of the object error: one per kErrPixelsPerBlock box pixels
+constexpr long long kErrPixelsPerBlock = 16384;
+inline int object_error_blocks(long long pixels) {
+  return int(pixels < 1 ? 1 : (pixels + kErrPixelsPerBlock - 1) / kErrPixelsPerBlock);
+}
+// The allocation-free object error keeps its partial sums in a static device
+// array of this many work-groups' sums (boxes of at most
+// kErrScratchBlocks * kErrPixelsPerBlock = 4096^2 pixels).
+constexpr int kErrScratchBlocks = 1024;
+hipError_t object_error_static(const float2* o, int ow, const float2* t, int r0, int c0, int h, int w,
+                               double* result, hipStream_t s);
 hipError_t launch_amp_prepare(int n, const float* intensity, float* amp, int J, int* bad, hipStream_t s);
 hipError_t launch_max_abs2_parts(const float2* a, size_t count, float* parts, int nparts, hipStream_t s);
 hipError_t launch_convert_state(int fp16, int to_store, const float2* src, void* dst_store,

@@ -136,3 +136,13 @@ def test_algorithmic_bytes_model():
     assert per_px(64, raar, "fp16", full=False, form="w") == 24
     # SF (a = 1) in the x form reads y only: 36 + 16 bytes
     assert per_px(128, sf, full=False) == 36
+
+
+def test_object_error_noalloc_checks_sizes_on_the_host(lib):
+    """Oversized or misplaced boxes are rejected from the sizes alone, before
+    any device call (the pointers here are never dereferenced)."""
+    fake = ctypes.c_void_p(256)
+    assert lib.pty_object_error_noalloc(fake, 4100, 4100, fake, 0, 0, 4100, 4100, fake, None) == 1
+    assert b"static scratch" in lib.pty_last_error()
+    assert lib.pty_object_error_noalloc(fake, 8, 8, fake, 4, 4, 8, 8, fake, None) == 1
+    assert lib.pty_object_error_noalloc(None, 8, 8, fake, 0, 0, 8, 8, fake, None) == 1
