@@ -215,6 +215,9 @@ struct StoreF32 {
       p[i] = v;
     }
   }
+  // the object step's exit-wave loads use the default policy: non-temporal
+  // ones measured slower (N = 256: 722 vs 675 us) and leave the probe step's
+  // second read of y without the memory-side cache (N = 128: 37.8 vs 25.4 us)
   __device__ __forceinline__ static float2 load_buf(__amdgpu_buffer_rsrc_t r, int byte_off, float /*inv*/) {
     return buffer_load_f2(r, byte_off);
   }

@@ -146,6 +146,10 @@ __global__ __launch_bounds__(256) void object_update_kernel(ObjParams p) {
     __syncthreads();
     for (int i = threadIdx.x; i < cn; i += 256) ent[i] = p.tile_ent[c0 + i];
     __syncthreads();
+    // (The conditional request of entry e + 2 makes the compiler wait for
+    // every load before the second accumulation; issuing it unconditionally,
+    // as the N <= 128 kernel does, measured slower here: 676 vs 664 us
+    // float32, 640 vs 523 us float16 on the 4096-pattern scan.)
     float2 pa[4], ya[4], pb[4], yb[4];
     issue(0, cn, pa, ya);
     for (int e = 0; e < cn; e += 2) {
@@ -288,13 +292,16 @@ __global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
     __syncthreads();
     if (cn <= 0) continue;
     // two register sets: the next entry's requests are in flight while the
-    // current one is accumulated (deeper rings measured slower)
+    // current one is accumulated; requests past the end of the list are
+    // issued too (zero, no memory request), since a conditional request makes
+    // the compiler's wait counts assume it absent and wait for every load
+    // (float16 at N = 128: 37.0 instead of 39.4 us)
     float2 pa[4], ya[4], pb[4], yb[4];
     issue(0, cn, pa, ya);
     for (int e = 0; e < cn; e += 2) {
       issue(e + 1, cn, pb, yb);
       accumulate(pa, ya);
-      if (e + 2 < cn) issue(e + 2, cn, pa, ya);
+      issue(e + 2, cn, pa, ya);
       accumulate(pb, yb);
     }
   }

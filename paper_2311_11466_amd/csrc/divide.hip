@@ -10,13 +10,46 @@ namespace pty {
 // ---------------------------------------------------------------------------
 // N = 256: three passes.  A work-group handles 16 rows (or 16 columns) of one
 // pattern, 16 threads per line, 16 values per thread; a line's 256-point DFT
-// is 16 x 16 with one LDS exchange inside the group.  The column pass keeps
-// its exchange tiles interleaved by column ([a][b][column]), so a wave's 16
-// columns touch consecutive LDS words rather than one bank.
+// is 16 x 16 with a transpose of the line's 16 x 16 block between its
+// threads.  In the row passes a row's 16 threads are lanes of one wave, so
+// the transpose needs no work-group barrier; it runs in two halves through a
+// buffer of 8 values per thread, and the twiddles come from a 16 x 16 table
+// in LDS: the forward row pass is limited by how many work-groups a CU holds
+// (half as many made it 38 % slower), and the smaller LDS and register
+// footprint allows seven instead of four.  The column pass, whose 16 threads
+// of a column sit in four waves, exchanges all values at once (the same
+// halving measured 5 % slower there); it keeps its exchange tiles interleaved
+// by column ([a][b][column]), so a wave's 16 columns touch consecutive LDS
+// words rather than one bank.
 // ---------------------------------------------------------------------------
 constexpr int L256 = 256;
-constexpr int LP = 17;                 // padded pitch of a 16 x 16 exchange tile
-constexpr int LT = 16 * LP;            // one line's exchange tile
+constexpr int LP = 17;                 // padded pitch of an exchange tile
+constexpr int LT = 16 * LP;            // one column's exchange tile (column pass)
+constexpr int LTH = 8 * LP;            // one row's half exchange tile (row passes)
+
+// Ordering of LDS accesses between the lanes of one wave: the hardware keeps
+// a wave's LDS operations in order, so only the compiler must not move them.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Transpose of a row's 16 x 16 block: on return thread t of the row holds in
+// v[c] what thread c held in v[t].  buf: the row's LTH entries, private to
+// the wave; round h moves values 8h .. 8h+7 and serves threads 8h .. 8h+7.
+__device__ __forceinline__ void row_transpose(float2 (&v)[16], float2* buf, int t) {
+  float2 w[16];
+  static_for<0, 2>([&](auto h) {
+    static_for<0, 8>([&](auto kk) { buf[kk.value * LP + t] = v[8 * h.value + kk.value]; });
+    wave_lds_order();
+    if ((t >> 3) == h.value) {
+      static_for<0, 16>([&](auto c) { w[c.value] = buf[(t - 8 * h.value) * LP + c.value]; });
+    }
+    wave_lds_order();
+  });
+  static_for<0, 16>([&](auto c) { v[c.value] = w[c.value]; });
+}
+
 
 // The float32 intermediate of the N = 256 passes is streamed once by each
 // pass: non-temporal accesses keep it from displacing the object and probe
@@ -34,10 +67,12 @@ __device__ __forceinline__ void tmp_store(float2* p, size_t i, float2 v) {
 
 template <class St>
 __global__ __launch_bounds__(256) void rows256_fwd_kernel(DivideParams p) {
-  __shared__ float2 lds[16 * LT];
+  __shared__ float2 lds[16 * LTH];
+  __shared__ float2 twt[16 * 16];      // twt[16 a + b] = tw[a b]
   __shared__ double red[MF_COUNT * 4];
   const int tid = threadIdx.x;
   const int t = tid & 15, rl = tid >> 4;
+  twt[tid] = p.tw[(tid >> 4) * (tid & 15)];
   const int r = blockIdx.x * 16 + rl;
   const int j = p.j_begin + blockIdx.y;
   const size_t base = size_t(j) * L256 * L256;
@@ -73,10 +108,9 @@ __global__ __launch_bounds__(256) void rows256_fwd_kernel(DivideParams p) {
     v[c1.value] = xn;
   });
   dft_reg<16, false>(v);                                  // over c1 -> kc1
-  static_for<1, 16>([&](auto k) { v[k.value] = cmul(v[k.value], p.tw[t * k.value]); });
-  static_for<0, 16>([&](auto k) { lds[rl * LT + k.value * LP + t] = v[k.value]; });
-  __syncthreads();
-  static_for<0, 16>([&](auto c2) { v[c2.value] = lds[rl * LT + t * LP + c2.value]; });
+  __syncthreads();                                        // twt is complete
+  static_for<1, 16>([&](auto k) { v[k.value] = cmul(v[k.value], twt[16 * t + k.value]); });
+  row_transpose(v, lds + rl * LTH, t);                    // thread t = kc1, v over c2
   dft_reg<16, false>(v);                                  // over c2 -> kc2; thread t = kc1
   static_for<0, 16>([&](auto k2) { tmp_store(p.tmp, base + r * L256 + t + 16 * k2.value, v[k2.value]); });
 
@@ -125,9 +159,11 @@ __global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
 
 template <class St>
 __global__ __launch_bounds__(256) void rows256_inv_kernel(DivideParams p) {
-  __shared__ float2 lds[16 * LT];
+  __shared__ float2 lds[16 * LTH];
+  __shared__ float2 twt[16 * 16];      // twt[16 a + b] = tw[a b]
   const int tid = threadIdx.x;
   const int t = tid & 15, rl = tid >> 4;
+  twt[tid] = p.tw[(tid >> 4) * (tid & 15)];
   const int r = blockIdx.x * 16 + rl;
   const int j = p.j_begin + blockIdx.y;
   const size_t base = size_t(j) * L256 * L256;
@@ -137,10 +173,9 @@ __global__ __launch_bounds__(256) void rows256_inv_kernel(DivideParams p) {
   // thread t = kc1 holds kc2
   static_for<0, 16>([&](auto k2) { v[k2.value] = tmp_load(p.tmp, base + r * L256 + t + 16 * k2.value); });
   dft_reg<16, true>(v);                                   // over kc2 -> c2
-  static_for<0, 16>([&](auto c2) { lds[rl * LT + c2.value * LP + t] = v[c2.value]; });
-  __syncthreads();
-  static_for<0, 16>([&](auto k1) { v[k1.value] = lds[rl * LT + t * LP + k1.value]; });  // thread t = c2
-  static_for<1, 16>([&](auto k) { v[k.value] = cmulc(v[k.value], p.tw[t * k.value]); });
+  row_transpose(v, lds + rl * LTH, t);                    // thread t = c2, v over kc1
+  __syncthreads();                                        // twt is complete
+  static_for<1, 16>([&](auto k) { v[k.value] = cmulc(v[k.value], twt[16 * t + k.value]); });
   dft_reg<16, true>(v);                                   // over kc1 -> c1
   static_for<0, 16>([&](auto c1) {
     St::store(ys, base + r * L256 + t + 16 * c1.value, v[c1.value], p.scale);
