@@ -278,8 +278,8 @@ pty_status launch_divide(pty_scan* s, const DivideParams& p, bool timed_launch) 
 // otherwise.  Every sweep's object launch writes the same metric slices and
 // every finalise the same ring entries (from mp), so repeating them is
 // harmless.
-pty_status launch_concur(pty_scan* s, const MetricParams& mp, bool update_probe, bool timed_launch) {
-  const hipStream_t st = s->stream;
+// Parameter blocks of the concur launches of one scan.
+void concur_params(const pty_scan* s, const MetricParams& mp, ObjParams* po, ProbeParams* pq) {
   ObjParams o{};
   o.y = s->ws + s->L.y;
   o.inv_scale = s->inv_scale;
@@ -305,6 +305,15 @@ pty_status launch_concur(pty_scan* s, const MetricParams& mp, bool update_probe,
   q.chunk = s->L.chunk;
   q.G = s->L.G;
   q.part = s->at<double>(s->L.part);
+  *po = o;
+  *pq = q;
+}
+
+pty_status launch_concur(pty_scan* s, const MetricParams& mp, bool update_probe, bool timed_launch) {
+  const hipStream_t st = s->stream;
+  ObjParams o;
+  ProbeParams q;
+  concur_params(s, mp, &o, &q);
   const FinalParams f = final_params(s, mp);
   const int n_sweeps = update_probe ? s->sweeps : 1;
   auto run = [&](int cls, auto&& fn) { return timed_launch ? timed(s, cls, fn) : fn(); };
@@ -327,7 +336,19 @@ bool use_blend(const pty_scan* s) {
   return !s->full_metrics && s->N <= 64 && float(1.0 - s->a) != 0.f && float(s->a * (1.0 - s->b)) != 0.f;
 }
 
-pty_status launch_iteration(pty_scan* s) {
+// One iteration of a scan, planned on the host: its divide parameters, the
+// metric bookkeeping of its concur launches, and the state it leaves.
+struct IterPlan {
+  DivideParams dp;
+  MetricParams mp;
+  bool update_probe;
+  bool wf;
+  bool write_x;
+};
+
+// Plan the next iteration (a change of state form first materialises x, which
+// launches the flush kernel on the scan's stream).
+pty_status plan_iteration(pty_scan* s, IterPlan* L) {
   const bool wf = use_blend(s);
   if ((wf && s->mode == MODE_PENDING) || (!wf && s->mode == MODE_PENDING_W)) {
     // a change of form passes through a materialised x
@@ -361,30 +382,138 @@ pty_status launch_iteration(pty_scan* s) {
   }
   p.write_x = write_x;
   p.c = float(s->c);
-  if (s->prof && s->ev_class.size() > 4096) PTY_HIP(s, drain_profile(s), "profile drain");
-  {
-    const pty_status ds = launch_divide(s, p, true);
-    if (ds != PTY_OK) return ds;
-  }
-
-  const bool update_probe = s->blind && s->k >= s->probe_update_start;
+  L->dp = p;
+  L->update_probe = s->blind && s->k >= s->probe_update_start;
   MetricParams mp = metric_params(s, object_blocks(s->N, s->L.n_tiles));
   mp.k_cur = s->k;
   mp.k_prev = (p.prev_ec || p.prev_dx) ? s->k - 1 : -1;
   mp.ec_ok = p.prev_ec;
   mp.dx_ok = p.prev_dx;
-  const pty_status cs = launch_concur(s, mp, update_probe, true);
-  if (cs != PTY_OK) return cs;
+  L->mp = mp;
+  L->wf = wf;
+  L->write_x = write_x;
+  return PTY_OK;
+}
 
-  // the new state is pending with this iteration's (a, b)
-  s->mode = wf ? MODE_PENDING_W : MODE_PENDING;
+// The state after the planned iteration's launches: pending with its (a, b).
+void commit_iteration(pty_scan* s, const IterPlan& L) {
+  s->mode = L.wf ? MODE_PENDING_W : MODE_PENDING;
   s->pa = float(s->a * s->b);
   s->pb = float(s->a * (1.0 - s->b));
   s->pg = float(1.0 - s->a);
-  s->x_valid = write_x;
+  s->x_valid = L.write_x;
   s->y_valid = true;
-  s->prev_metrics_done = wf;   // the blend form has no consistency / change metrics
+  s->prev_metrics_done = L.wf;   // the blend form has no consistency / change metrics
   s->k += 1;
+}
+
+pty_status launch_iteration(pty_scan* s) {
+  IterPlan L;
+  pty_status st = plan_iteration(s, &L);
+  if (st != PTY_OK) return st;
+  if (s->prof && s->ev_class.size() > 4096) PTY_HIP(s, drain_profile(s), "profile drain");
+  st = launch_divide(s, L.dp, true);
+  if (st != PTY_OK) return st;
+  st = launch_concur(s, L.mp, L.update_probe, true);
+  if (st != PTY_OK) return st;
+  commit_iteration(s, L);
+  return PTY_OK;
+}
+
+// One iteration of several scans on one stream with grouped launches: every
+// kernel class runs once per group of up to kGroupMax scans of the same
+// pattern size and storage (and, for the divide, the same prologue mode)
+// instead of once per scan.  Each scan's kernels see exactly the parameters
+// of its own launch, so its results are bitwise those of pty_iterate.
+pty_status launch_iteration_grouped(pty_scan* const* scans, int count) {
+  std::vector<IterPlan> plans(count);
+  for (int i = 0; i < count; ++i) {
+    const pty_status st = plan_iteration(scans[i], &plans[i]);
+    if (st != PTY_OK) return st;
+  }
+  const hipStream_t stream = scans[0]->stream;
+  // scans in call order, grouped by key; groups are launched in order of
+  // their first scan, each in chunks of kGroupMax
+  auto run_groups = [&](auto key_of, auto launch_chunk) -> pty_status {
+    std::vector<char> done(count, 0);
+    for (int i = 0; i < count; ++i) {
+      if (done[i]) continue;
+      const auto key = key_of(i);
+      std::vector<int> members;
+      for (int q = i; q < count; ++q)
+        if (!done[q] && key_of(q) == key) { members.push_back(q); done[q] = 1; }
+      for (size_t c = 0; c < members.size(); c += kGroupMax) {
+        const int n = int(std::min<size_t>(kGroupMax, members.size() - c));
+        const pty_status st = launch_chunk(members.data() + c, n);
+        if (st != PTY_OK) return st;
+      }
+    }
+    return PTY_OK;
+  };
+  // divide
+  for (int stage = 0; stage < 3; ++stage) {
+    auto key = [&](int i) {
+      const pty_scan* s = scans[i];
+      if (stage >= divide_stages(s->N)) return -1;                 // no such stage for this scan
+      if (!divide_groupable(s->N, plans[i].dp)) return -2 - i;     // alone
+      return ((s->N * 2 + s->fp16) * 64) + (s->N == 256 ? 0 : divide_mode(plans[i].dp));
+    };
+    const pty_status st = run_groups(key, [&](const int* m, int n) -> pty_status {
+      if (key(m[0]) == -1) return PTY_OK;
+      pty_scan* s0 = scans[m[0]];
+      if (key(m[0]) < -1) {
+        const hipError_t e = launch_divide_stage(s0->N, s0->fp16, plans[m[0]].dp, s0->J, stage, stream);
+        return e == hipSuccess ? PTY_OK : device_fail(s0, e, "divide launch");
+      }
+      DivideParams ps[kGroupMax];
+      int np[kGroupMax];
+      for (int q = 0; q < n; ++q) { ps[q] = plans[m[q]].dp; np[q] = scans[m[q]]->J; }
+      const hipError_t e = launch_divide_stage_group(s0->N, s0->fp16, ps, np, n, stage, stream);
+      return e == hipSuccess ? PTY_OK : device_fail(s0, e, "grouped divide launch");
+    });
+    if (st != PTY_OK) return st;
+  }
+  // concur: object steps, probe sums (scans whose probe is updated), finalise;
+  // a scan with several concur sweeps runs its own launches
+  auto swept = [&](int i) { return plans[i].update_probe && scans[i]->sweeps > 1; };
+  pty_status st = run_groups([&](int i) { return swept(i) ? -1 - i : scans[i]->N * 2 + scans[i]->fp16; },
+                             [&](const int* m, int n) -> pty_status {
+    pty_scan* s0 = scans[m[0]];
+    if (swept(m[0])) return launch_concur(s0, plans[m[0]].mp, true, false);
+    ObjParams os[kGroupMax];
+    for (int q = 0; q < n; ++q) {
+      ProbeParams unused;
+      concur_params(scans[m[q]], plans[m[q]].mp, &os[q], &unused);
+    }
+    const hipError_t e = launch_object_update_group(s0->fp16, os, n, stream);
+    return e == hipSuccess ? PTY_OK : device_fail(s0, e, "grouped object launch");
+  });
+  if (st != PTY_OK) return st;
+  st = run_groups([&](int i) { return (swept(i) || !plans[i].update_probe) ? -1 : scans[i]->N * 2 + scans[i]->fp16; },
+                  [&](const int* m, int n) -> pty_status {
+    if (swept(m[0]) || !plans[m[0]].update_probe) return PTY_OK;
+    ProbeParams qs[kGroupMax];
+    for (int q = 0; q < n; ++q) {
+      ObjParams unused;
+      concur_params(scans[m[q]], plans[m[q]].mp, &unused, &qs[q]);
+    }
+    const hipError_t e = launch_probe_partial_group(scans[m[0]]->fp16, qs, n, stream);
+    return e == hipSuccess ? PTY_OK : device_fail(scans[m[0]], e, "grouped probe launch");
+  });
+  if (st != PTY_OK) return st;
+  st = run_groups([&](int i) { return swept(i) ? -1 : 0; }, [&](const int* m, int n) -> pty_status {
+    if (swept(m[0])) return PTY_OK;
+    FinalParams fs[kGroupMax];
+    int up[kGroupMax];
+    for (int q = 0; q < n; ++q) {
+      fs[q] = final_params(scans[m[q]], plans[m[q]].mp);
+      up[q] = plans[m[q]].update_probe ? 1 : 0;
+    }
+    const hipError_t e = launch_probe_final_group(fs, up, n, stream);
+    return e == hipSuccess ? PTY_OK : device_fail(scans[m[0]], e, "grouped finalise launch");
+  });
+  if (st != PTY_OK) return st;
+  for (int i = 0; i < count; ++i) commit_iteration(scans[i], plans[i]);
   return PTY_OK;
 }
 
@@ -725,8 +854,16 @@ pty_status pty_iterate_many(pty_scan* const* scans, int32_t count, int32_t n) {
     for (int32_t q = 0; q < i; ++q)
       if (scans[q] == scans[i]) return fail(PTY_ERR_INVALID_ARG, "a scan is listed twice");
   }
+  bool grouped = count > 1;
+  for (int32_t i = 0; i < count && grouped; ++i)
+    grouped = scans[i]->stream == scans[0]->stream && !scans[i]->prof;
   try {
     for (int32_t it = 0; it < n; ++it) {
+      if (grouped) {
+        const pty_status st = launch_iteration_grouped(scans, count);
+        if (st != PTY_OK) return st;
+        continue;
+      }
       for (int32_t i = 0; i < count; ++i) {
         pty_status st = launch_iteration(scans[i]);
         if (st != PTY_OK) return st;

@@ -85,12 +85,14 @@ __global__ __launch_bounds__(256) void metric_slice_kernel(MetricParams p) {
 // requests are in flight while the current one is accumulated.
 constexpr int kListChunk = 256;
 
+// blk, grid: the work-group's index and the (multiple of 8) work-group count
+// of its scan's launch
 template <class St>
-__global__ __launch_bounds__(256) void object_update_kernel(ObjParams p) {
+__device__ __forceinline__ void object_update_body(const ObjParams& p, const int blk, const int grid) {
   __shared__ float red[4];
   __shared__ int4 ent[kListChunk];     // (scan index, row offset, col offset, unused)
   __shared__ double mred[MF_COUNT * 4];
-  const int tile = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
+  const int tile = xcd_block(blk, grid);   // neighbouring tiles on one XCD
   if (tile >= p.n_tiles) return;
   const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -184,16 +186,20 @@ __global__ __launch_bounds__(256) void object_update_kernel(ObjParams p) {
 // request), so it adds exactly zero.  Tile maxima and metric slices are per
 // work-group.
 constexpr int kGroupTiles = 4;
+#ifndef PTY_OBJ_RING
+#define PTY_OBJ_RING 2
+#endif
+constexpr int kObjRing = PTY_OBJ_RING;   // list entries in flight per wave
 
 template <class St, int N>
-__global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
+__device__ __forceinline__ void object_lds_body(const ObjParams& p, const int blk_id, const int grid) {
   constexpr int NN = N * N;
   constexpr int kZero = NN;            // index of the zero probe entry
   __shared__ float2 pl[NN + 1];
   __shared__ int4 ent[kGroupTiles][kListChunk];
   __shared__ float red[16];
   __shared__ int cnt[kGroupTiles];
-  const int blk = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles on one XCD
+  const int blk = xcd_block(blk_id, grid);   // neighbouring tiles on one XCD
   if (blk >= (p.n_tiles + kGroupTiles - 1) / kGroupTiles) return;
   const int g = threadIdx.x >> 8, lt = threadIdx.x & 255;
   const int tile = blk * kGroupTiles + g;
@@ -291,18 +297,18 @@ __global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
     for (int i = lt; i < cn; i += 256) ent[g][i] = p.tile_ent[e0 + c0 + i];
     __syncthreads();
     if (cn <= 0) continue;
-    // two register sets: the next entry's requests are in flight while the
-    // current one is accumulated; requests past the end of the list are
-    // issued too (zero, no memory request), since a conditional request makes
-    // the compiler's wait counts assume it absent and wait for every load
-    // (float16 at N = 128: 37.0 instead of 39.4 us)
-    float2 pa[4], ya[4], pb[4], yb[4];
-    issue(0, cn, pa, ya);
-    for (int e = 0; e < cn; e += 2) {
-      issue(e + 1, cn, pb, yb);
-      accumulate(pa, ya);
-      issue(e + 2, cn, pa, ya);
-      accumulate(pb, yb);
+    // a ring of kObjRing register sets: the following entries' requests are
+    // in flight while one is accumulated, in list order; requests past the
+    // end of the list are issued too (zero, no memory request, adding exactly
+    // zero), since a conditional request makes the compiler's wait counts
+    // assume it absent and wait for every load
+    float2 pr[kObjRing][4], yr[kObjRing][4];
+    static_for<0, kObjRing>([&](auto q) { issue(q.value, cn, pr[q.value], yr[q.value]); });
+    for (int e = 0; e < cn; e += kObjRing) {
+      static_for<0, kObjRing>([&](auto q) {
+        accumulate(pr[q.value], yr[q.value]);
+        issue(e + kObjRing + q.value, cn, pr[q.value], yr[q.value]);
+      });
     }
   }
   float m = 0.0f;
@@ -325,13 +331,13 @@ __global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
 constexpr int kProbeUnroll = 8;
 
 template <class St>
-__global__ __launch_bounds__(256) void probe_partial_kernel(ProbeParams p) {
+__device__ __forceinline__ void probe_partial_body(const ProbeParams& p, const int blk, const int grid) {
   const int N = p.N;
   const int NN = N * N;
   // logical block = chunk-major (g, pixel block); each XCD runs whole chunks,
   // whose object gathers then stay in its L2
   const int npb = (NN + 255) / 256;
-  const int l = xcd_block(blockIdx.x, gridDim.x);
+  const int l = xcd_block(blk, grid);
   if (l >= npb * p.G) return;
   const int g = l / npb;
   const int u = (l % npb) * 256 + threadIdx.x;
@@ -371,10 +377,10 @@ __global__ __launch_bounds__(256) void probe_partial_kernel(ProbeParams p) {
   }
 }
 
-__global__ __launch_bounds__(256) void probe_final_kernel(FinalParams p) {
+__device__ __forceinline__ void probe_final_body(const FinalParams& p, const int blk) {
   __shared__ double dred[MF_COUNT * 4];
   __shared__ float fred[4];
-  const int b = blockIdx.x + p.first_block;
+  const int b = blk + p.first_block;
   if (b == p.npb) {
     metric_finish(p.mp, dred);
     return;
@@ -423,6 +429,45 @@ __global__ __launch_bounds__(256) void probe_final_kernel(FinalParams p) {
   if (threadIdx.x == 0) p.pmax_part[b] = m;
 }
 
+// Kernels: one scan, or a group of scans in one launch (the served form),
+// with the same per-work-group work.
+template <class St>
+__global__ __launch_bounds__(256) void object_update_kernel(ObjParams p) {
+  object_update_body<St>(p, int(blockIdx.x), int(gridDim.x));
+}
+template <class St>
+__global__ __launch_bounds__(256) void object_update_group_kernel(Group<ObjParams> g) {
+  const int b = int(blockIdx.x);
+  const int sc = group_scan(g, b);
+  object_update_body<St>(g.p[sc], b - g.first[sc], g.first[sc + 1] - g.first[sc]);
+}
+template <class St, int N>
+__global__ __launch_bounds__(1024) void object_lds_kernel(ObjParams p) {
+  object_lds_body<St, N>(p, int(blockIdx.x), int(gridDim.x));
+}
+template <class St, int N>
+__global__ __launch_bounds__(1024) void object_lds_group_kernel(Group<ObjParams> g) {
+  const int b = int(blockIdx.x);
+  const int sc = group_scan(g, b);
+  object_lds_body<St, N>(g.p[sc], b - g.first[sc], g.first[sc + 1] - g.first[sc]);
+}
+template <class St>
+__global__ __launch_bounds__(256) void probe_partial_kernel(ProbeParams p) {
+  probe_partial_body<St>(p, int(blockIdx.x), int(gridDim.x));
+}
+template <class St>
+__global__ __launch_bounds__(256) void probe_partial_group_kernel(Group<ProbeParams> g) {
+  const int b = int(blockIdx.x);
+  const int sc = group_scan(g, b);
+  probe_partial_body<St>(g.p[sc], b - g.first[sc], g.first[sc + 1] - g.first[sc]);
+}
+__global__ __launch_bounds__(256) void probe_final_kernel(FinalParams p) { probe_final_body(p, int(blockIdx.x)); }
+__global__ __launch_bounds__(256) void probe_final_group_kernel(Group<FinalParams> g) {
+  const int b = int(blockIdx.x);
+  const int sc = group_scan(g, b);
+  probe_final_body(g.p[sc], b - g.first[sc]);
+}
+
 __global__ __launch_bounds__(256) void max_abs2_parts_kernel(const float2* a, size_t count, float* parts) {
   __shared__ float red[4];
   float m = 0.0f;
@@ -469,6 +514,73 @@ hipError_t launch_probe_partial(int fp16, const ProbeParams& p, hipStream_t s) {
   const dim3 grid(xcd_pad((p.N * p.N + 255) / 256 * p.G));
   if (fp16) hipLaunchKernelGGL(probe_partial_kernel<StoreF16>, grid, dim3(256), 0, s, p);
   else hipLaunchKernelGGL(probe_partial_kernel<StoreF32>, grid, dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+// Grouped launchers: every scan's range of work-groups is the count its own
+// launch would use (a multiple of 8 where the work-groups are mapped to
+// XCD-contiguous ranges), one after the other.
+hipError_t launch_object_update_group(int fp16, const ObjParams* ps, int count, hipStream_t s) {
+  if (count < 1 || count > kGroupMax) return hipErrorInvalidValue;
+  Group<ObjParams> g{};
+  int blocks = 0;
+  for (int i = 0; i < count; ++i) {
+    if (ps[i].N != ps[0].N) return hipErrorInvalidValue;
+    g.p[i] = ps[i];
+    g.first[i] = blocks;
+    blocks += xcd_pad(object_blocks(ps[i].N, ps[i].n_tiles));
+  }
+  g.first[count] = blocks;
+  g.count = count;
+  const int N = ps[0].N;
+  const dim3 grid(blocks);
+  if (fp16) {
+    switch (N) {
+      case 32: hipLaunchKernelGGL((object_lds_group_kernel<StoreF16, 32>), grid, dim3(1024), 0, s, g); break;
+      case 64: hipLaunchKernelGGL((object_lds_group_kernel<StoreF16, 64>), grid, dim3(1024), 0, s, g); break;
+      case 128: hipLaunchKernelGGL((object_lds_group_kernel<StoreF16, 128>), grid, dim3(1024), 0, s, g); break;
+      default: hipLaunchKernelGGL(object_update_group_kernel<StoreF16>, grid, dim3(256), 0, s, g); break;
+    }
+  } else {
+    switch (N) {
+      case 32: hipLaunchKernelGGL((object_lds_group_kernel<StoreF32, 32>), grid, dim3(1024), 0, s, g); break;
+      case 64: hipLaunchKernelGGL((object_lds_group_kernel<StoreF32, 64>), grid, dim3(1024), 0, s, g); break;
+      case 128: hipLaunchKernelGGL((object_lds_group_kernel<StoreF32, 128>), grid, dim3(1024), 0, s, g); break;
+      default: hipLaunchKernelGGL(object_update_group_kernel<StoreF32>, grid, dim3(256), 0, s, g); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_partial_group(int fp16, const ProbeParams* ps, int count, hipStream_t s) {
+  if (count < 1 || count > kGroupMax) return hipErrorInvalidValue;
+  Group<ProbeParams> g{};
+  int blocks = 0;
+  for (int i = 0; i < count; ++i) {
+    g.p[i] = ps[i];
+    g.first[i] = blocks;
+    blocks += xcd_pad((ps[i].N * ps[i].N + 255) / 256 * ps[i].G);
+  }
+  g.first[count] = blocks;
+  g.count = count;
+  if (fp16) hipLaunchKernelGGL(probe_partial_group_kernel<StoreF16>, dim3(blocks), dim3(256), 0, s, g);
+  else hipLaunchKernelGGL(probe_partial_group_kernel<StoreF32>, dim3(blocks), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_final_group(const FinalParams* ps, const int* update_probe, int count, hipStream_t s) {
+  if (count < 1 || count > kGroupMax) return hipErrorInvalidValue;
+  Group<FinalParams> g{};
+  int blocks = 0;
+  for (int i = 0; i < count; ++i) {
+    g.p[i] = ps[i];
+    g.p[i].first_block = update_probe[i] ? 0 : ps[i].npb;
+    g.first[i] = blocks;
+    blocks += update_probe[i] ? ps[i].npb + 1 : 1;
+  }
+  g.first[count] = blocks;
+  g.count = count;
+  hipLaunchKernelGGL(probe_final_group_kernel, dim3(blocks), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

@@ -3,7 +3,7 @@
 // size).
 #include <algorithm>
 
-#include "divide_ops.hpp"
+#include "divide_fused.hpp"
 
 namespace pty {
 
@@ -65,16 +65,17 @@ __device__ __forceinline__ void tmp_store(float2* p, size_t i, float2 v) {
   __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(p) + i);
 }
 
+// rb: the work-group's block of 16 rows, jl: its pattern within the launch
 template <class St>
-__global__ __launch_bounds__(256) void rows256_fwd_kernel(DivideParams p) {
+__device__ __forceinline__ void rows256_fwd_body(const DivideParams& p, const int rb, const int jl) {
   __shared__ float2 lds[16 * LTH];
   __shared__ float2 twt[16 * 16];      // twt[16 a + b] = tw[a b]
   __shared__ double red[MF_COUNT * 4];
   const int tid = threadIdx.x;
   const int t = tid & 15, rl = tid >> 4;
   twt[tid] = p.tw[(tid >> 4) * (tid & 15)];
-  const int r = blockIdx.x * 16 + rl;
-  const int j = p.j_begin + blockIdx.y;
+  const int r = rb * 16 + rl;
+  const int j = p.j_begin + jl;
   const size_t base = size_t(j) * L256 * L256;
   const int2 pj = p.pos[j];
   using elem = typename St::elem;
@@ -116,16 +117,16 @@ __global__ __launch_bounds__(256) void rows256_fwd_kernel(DivideParams p) {
 
   block_sum<MF_COUNT, 256>(acc, red);
   if (tid >= MF_EC_NUM && tid < MF_COUNT)
-    p.met[(size_t(j) * p.nslot + blockIdx.x) * MF_COUNT + tid] = acc[tid];
+    p.met[(size_t(j) * p.nslot + rb) * MF_COUNT + tid] = acc[tid];
 }
 
-__global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
+__device__ __forceinline__ void cols256_body(const DivideParams& p, const int cb, const int jl) {
   __shared__ float2 lds[16 * LT];
   __shared__ double red[2 * 4];
   const int tid = threadIdx.x;
   const int cl = tid & 15, t = tid >> 4;
-  const int col = blockIdx.x * 16 + cl;
-  const int j = p.j_begin + blockIdx.y;
+  const int col = cb * 16 + cl;
+  const int j = p.j_begin + jl;
   const size_t base = size_t(j) * L256 * L256;
   float2 v[16];
   // rows r = t + 16 r1
@@ -154,18 +155,18 @@ __global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
   static_for<0, 16>([&](auto r1) { tmp_store(p.tmp, base + (t + 16 * r1.value) * L256 + col, v[r1.value]); });
 
   block_sum<2, 256>(acc, red);
-  if (tid < 2) p.met[(size_t(j) * p.nslot + blockIdx.x) * MF_COUNT + tid] = acc[tid];
+  if (tid < 2) p.met[(size_t(j) * p.nslot + cb) * MF_COUNT + tid] = acc[tid];
 }
 
 template <class St>
-__global__ __launch_bounds__(256) void rows256_inv_kernel(DivideParams p) {
+__device__ __forceinline__ void rows256_inv_body(const DivideParams& p, const int rb, const int jl) {
   __shared__ float2 lds[16 * LTH];
   __shared__ float2 twt[16 * 16];      // twt[16 a + b] = tw[a b]
   const int tid = threadIdx.x;
   const int t = tid & 15, rl = tid >> 4;
   twt[tid] = p.tw[(tid >> 4) * (tid & 15)];
-  const int r = blockIdx.x * 16 + rl;
-  const int j = p.j_begin + blockIdx.y;
+  const int r = rb * 16 + rl;
+  const int j = p.j_begin + jl;
   const size_t base = size_t(j) * L256 * L256;
   using elem = typename St::elem;
   elem* __restrict__ ys = reinterpret_cast<elem*>(p.y);
@@ -180,6 +181,29 @@ __global__ __launch_bounds__(256) void rows256_inv_kernel(DivideParams p) {
   static_for<0, 16>([&](auto c1) {
     St::store(ys, base + r * L256 + t + 16 * c1.value, v[c1.value], p.scale);
   });
+}
+
+// One scan: grid (16, patterns).  Grouped (the served form): a flat grid, 16
+// consecutive work-groups per pattern.
+template <class St>
+__global__ __launch_bounds__(256) void rows256_fwd_kernel(DivideParams p) {
+  rows256_fwd_body<St>(p, int(blockIdx.x), int(blockIdx.y));
+}
+__global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
+  cols256_body(p, int(blockIdx.x), int(blockIdx.y));
+}
+template <class St>
+__global__ __launch_bounds__(256) void rows256_inv_kernel(DivideParams p) {
+  rows256_inv_body<St>(p, int(blockIdx.x), int(blockIdx.y));
+}
+template <class St, int STAGE>
+__global__ __launch_bounds__(256) void pass256_group_kernel(Group<DivideParams> g) {
+  const int b = int(blockIdx.x);
+  const int sc = group_scan(g, b);
+  const int l = b - g.first[sc];
+  if (STAGE == 0) rows256_fwd_body<St>(g.p[sc], l & 15, l >> 4);
+  if (STAGE == 1) cols256_body(g.p[sc], l & 15, l >> 4);
+  if (STAGE == 2) rows256_inv_body<St>(g.p[sc], l & 15, l >> 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -326,6 +350,43 @@ static hipError_t launch_256_stage(const DivideParams& p, int n_patterns, int st
   return hipGetLastError();
 }
 
+template <class St>
+static hipError_t launch_256_stage_group(const Group<DivideParams>& g, int blocks, int stage, hipStream_t s) {
+  if (g.p[0].wform) return hipErrorInvalidValue;
+  switch (stage) {
+    case 0: hipLaunchKernelGGL((pass256_group_kernel<St, 0>), dim3(blocks), dim3(256), 0, s, g); break;
+    case 1: hipLaunchKernelGGL((pass256_group_kernel<St, 1>), dim3(blocks), dim3(256), 0, s, g); break;
+    case 2: hipLaunchKernelGGL((pass256_group_kernel<St, 2>), dim3(blocks), dim3(256), 0, s, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_divide_stage_group(int n, int fp16, const DivideParams* ps, const int* n_patterns, int count,
+                                     int stage, hipStream_t s) {
+  if (count < 1 || count > kGroupMax) return hipErrorInvalidValue;
+  Group<DivideParams> g{};
+  const int per_pattern = n == 256 ? 16 : 1;     // work-groups per pattern
+  int blocks = 0;
+  for (int i = 0; i < count; ++i) {
+    g.p[i] = ps[i];
+    g.first[i] = blocks;
+    blocks += per_pattern * n_patterns[i];
+  }
+  g.first[count] = blocks;
+  g.count = count;
+  if (blocks <= 0) return hipSuccess;
+  if (n == 256) return fp16 ? launch_256_stage_group<StoreF16>(g, blocks, stage, s)
+                            : launch_256_stage_group<StoreF32>(g, blocks, stage, s);
+  if (stage != 0) return hipErrorInvalidValue;
+  switch (n) {
+    case 32: return launch_fused_group_n32(fp16, g, blocks, s);
+    case 64: return launch_fused_group_n64(fp16, g, blocks, s);
+    case 128: return launch_fused_group_n128(fp16, g, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_divide_stage(int n, int fp16, const DivideParams& p, int n_patterns, int stage, hipStream_t s) {
   if (n_patterns <= 0) return hipSuccess;
   if (n != 256) return stage == 0 ? launch_fused_any(n, fp16, p, n_patterns, s) : hipErrorInvalidValue;
@@ -333,6 +394,19 @@ hipError_t launch_divide_stage(int n, int fp16, const DivideParams& p, int n_pat
 }
 
 int divide_stages(int n) { return n == 256 ? 3 : 1; }
+
+int divide_mode(const DivideParams& p) { return prologue_mode(p); }
+
+bool divide_groupable(int n, const DivideParams& p) {
+  if (n == 256) return !p.wform;
+  switch (prologue_mode(p)) {
+    case PRO_GENERAL: case PRO_UPDATE: case PRO_INIT: case PRO_W_PENDING: case PRO_W_ZERO:
+    case PRO_Z: case PRO_Y_EC: case PRO_Y:
+      return true;
+    default:
+      return false;
+  }
+}
 
 int divide_slots(int n) { return n == 256 ? 16 : 1; }
 bool divide_supported(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }

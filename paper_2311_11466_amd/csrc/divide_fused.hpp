@@ -135,9 +135,10 @@ constexpr bool split_exchange() {
   return N == 128 && MODE != PRO_FLAGS && !Pro<MODE>::wf;
 }
 
+// The divide of one pattern by one work-group; blk is the work-group's index
+// within its scan's launch (the batch slot for sequential projections).
 template <int N, int T, class St, int MODE>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(split_exchange<N, MODE>() ? 4 : 2)))
-void divide_fused_kernel(DivideParams p) {
+__device__ __forceinline__ void divide_fused_body(const DivideParams& p, const int blk) {
   using G = DivGeom<N, T>;
   using PR = Pro<MODE>;
   constexpr int M = G::M, E = G::E, SA = G::SA, SB = G::SB, PA = G::PA, PB = G::PB, PB2 = G::PB2;
@@ -147,7 +148,7 @@ void divide_fused_kernel(DivideParams p) {
   __shared__ double red[MF_COUNT * (T / 64)];
 
   const unsigned tid = threadIdx.x;
-  const int j = PR::sp ? p.batch[blockIdx.x] : p.j_begin + int(blockIdx.x);
+  const int j = PR::sp ? p.batch[blk] : p.j_begin + blk;
   const size_t base = size_t(j) * (N * N);
   const int2 pj = p.pos[j];
   using elem = typename St::elem;
@@ -387,7 +388,7 @@ void divide_fused_kernel(DivideParams p) {
           ob_out[r * ow + c] = make_float2(fmaf(sp_ka, po.x, oo[q.value].x), fmaf(sp_ka, po.y, oo[q.value].y));
           if (p.sp_blind) {
             const float2 oc = cmulc(d, oo[q.value]);     // conj(S_j O) d
-            p.contrib[size_t(blockIdx.x) * (N * N) + r * N + c] = make_float2(sp_kb * oc.x, sp_kb * oc.y);
+            p.contrib[size_t(blk) * (N * N) + r * N + c] = make_float2(sp_kb * oc.x, sp_kb * oc.y);
           }
         });
         __builtin_amdgcn_sched_barrier(0);
@@ -452,6 +453,21 @@ void divide_fused_kernel(DivideParams p) {
 }
 
 template <int N, int T, class St, int MODE>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(split_exchange<N, MODE>() ? 4 : 2)))
+void divide_fused_kernel(DivideParams p) {
+  divide_fused_body<N, T, St, MODE>(p, int(blockIdx.x));
+}
+
+// Several scans in one launch (the served form): the same per-pattern work.
+template <int N, int T, class St, int MODE>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(split_exchange<N, MODE>() ? 4 : 2)))
+void divide_fused_group_kernel(Group<DivideParams> g) {
+  const int b = int(blockIdx.x);
+  const int sc = group_scan(g, b);
+  divide_fused_body<N, T, St, MODE>(g.p[sc], b - g.first[sc]);
+}
+
+template <int N, int T, class St, int MODE>
 static void launch_fused_mode(const DivideParams& p, int n_patterns, hipStream_t s) {
   // plain order: consecutive patterns round-robin over the XCDs measured faster
   // here than XCD-contiguous ranges (xcd_block)
@@ -476,12 +492,40 @@ static hipError_t launch_fused(const DivideParams& p, int n_patterns, hipStream_
   return hipGetLastError();
 }
 
-// Entry points of one size: the divide in every prologue mode, and the
-// sequential-projection batch kernel.
+template <int N, int T, class St, int MODE>
+static void launch_fused_group_mode(const Group<DivideParams>& g, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((divide_fused_group_kernel<N, T, St, MODE>), dim3(blocks), dim3(T), 0, s, g);
+}
+
+// Grouped launches exist for the compile-time modes of the iteration's steady
+// state and first step; others return hipErrorInvalidValue (the host launches
+// such scans one by one).
+template <int N, int T, class St>
+static hipError_t launch_fused_group(const Group<DivideParams>& g, int blocks, hipStream_t s) {
+  switch (prologue_mode(g.p[0])) {
+    case PRO_GENERAL: launch_fused_group_mode<N, T, St, PRO_GENERAL>(g, blocks, s); break;
+    case PRO_UPDATE: launch_fused_group_mode<N, T, St, PRO_UPDATE>(g, blocks, s); break;
+    case PRO_INIT: launch_fused_group_mode<N, T, St, PRO_INIT>(g, blocks, s); break;
+    case PRO_W_PENDING: launch_fused_group_mode<N, T, St, PRO_W_PENDING>(g, blocks, s); break;
+    case PRO_W_ZERO: launch_fused_group_mode<N, T, St, PRO_W_ZERO>(g, blocks, s); break;
+    case PRO_Z: launch_fused_group_mode<N, T, St, PRO_Z>(g, blocks, s); break;
+    case PRO_Y_EC: launch_fused_group_mode<N, T, St, PRO_Y_EC>(g, blocks, s); break;
+    case PRO_Y: launch_fused_group_mode<N, T, St, PRO_Y>(g, blocks, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Entry points of one size: the divide in every prologue mode (alone and
+// grouped), and the sequential-projection batch kernel.
 #define PTY_DEFINE_FUSED(NN, TT)                                                            \
   hipError_t launch_fused_n##NN(int fp16, const DivideParams& p, int n_patterns, hipStream_t s) { \
     return fp16 ? launch_fused<NN, TT, StoreF16>(p, n_patterns, s)                          \
                 : launch_fused<NN, TT, StoreF32>(p, n_patterns, s);                         \
+  }                                                                                         \
+  hipError_t launch_fused_group_n##NN(int fp16, const Group<DivideParams>& g, int blocks, hipStream_t s) { \
+    return fp16 ? launch_fused_group<NN, TT, StoreF16>(g, blocks, s)                        \
+                : launch_fused_group<NN, TT, StoreF32>(g, blocks, s);                       \
   }                                                                                         \
   hipError_t launch_sp_n##NN(const DivideParams& p, int count, hipStream_t s) {             \
     launch_fused_mode<NN, TT, StoreF32, PRO_SP>(p, count, s);                               \

@@ -136,16 +136,49 @@ struct FlushParams {
   int wform;              // x holds the blend w: x = alpha * P S_j O + w, no metrics
 };
 
+// Grouped launch: one launch runs the same kernel for up to kGroupMax scans
+// (same pattern size, storage and prologue mode); scan s owns the launch's
+// work-groups [first[s], first[s+1]), each block range a multiple of 8 so that
+// a block's XCD is the same as in a launch of its scan alone.
+constexpr int kGroupMax = 8;
+template <class P>
+struct Group {
+  P p[kGroupMax];
+  int first[kGroupMax + 1];
+  int count;
+};
+// The scan of work-group b in a grouped launch: the last s with first[s] <= b
+// (a few scalar comparisons; first[] is in the kernel arguments).
+template <class P>
+__device__ __forceinline__ int group_scan(const Group<P>& g, int b) {
+  int s = 0;
+#pragma unroll
+  for (int i = 1; i < kGroupMax; ++i) s += (i < g.count && b >= g.first[i]) ? 1 : 0;
+  return s;
+}
+
 // ---- launchers (return hipGetLastError() of the launch) ----
 // one kernel of the divide: stage 0 (fused, or N = 256 rows forward), 1 (N = 256 columns), 2 (N = 256 rows inverse)
 hipError_t launch_divide_stage(int n, int fp16, const DivideParams& p, int n_patterns, int stage, hipStream_t s);
+// the same stage for count <= kGroupMax scans in one launch (ps[i] with n_patterns[i]
+// patterns; every ps[i] has the prologue mode of ps[0])
+hipError_t launch_divide_stage_group(int n, int fp16, const DivideParams* ps, const int* n_patterns, int count,
+                                     int stage, hipStream_t s);
 int divide_stages(int n);
+// the prologue mode a divide launch with these parameters runs (scans are
+// grouped only with scans of the same mode)
+int divide_mode(const DivideParams& p);
+// whether a divide launch with these parameters has a grouped form
+bool divide_groupable(int n, const DivideParams& p);
 hipError_t launch_object_update(int fp16, const ObjParams& p, hipStream_t s);
+hipError_t launch_object_update_group(int fp16, const ObjParams* ps, int count, hipStream_t s);
 // work-groups of the object launch: each writes one tile_max entry and one metric slice
 int object_blocks(int n, int n_tiles);
 hipError_t launch_probe_partial(int fp16, const ProbeParams& p, hipStream_t s);
+hipError_t launch_probe_partial_group(int fp16, const ProbeParams* ps, int count, hipStream_t s);
 hipError_t launch_flush(int fp16, const FlushParams& p, int J, hipStream_t s);
 hipError_t launch_probe_final(const FinalParams& p, int update_probe, hipStream_t s);
+hipError_t launch_probe_final_group(const FinalParams* ps, const int* update_probe, int count, hipStream_t s);
 hipError_t launch_metric_slices(const MetricParams& p, hipStream_t s);
 hipError_t launch_swap(float2* a, float2* b, size_t count, hipStream_t s);
 hipError_t launch_sp_batch(int n, const DivideParams& p, int count, hipStream_t s);
@@ -153,6 +186,9 @@ hipError_t launch_sp_batch(int n, const DivideParams& p, int count, hipStream_t 
 hipError_t launch_fused_n32(int fp16, const DivideParams& p, int n_patterns, hipStream_t s);
 hipError_t launch_fused_n64(int fp16, const DivideParams& p, int n_patterns, hipStream_t s);
 hipError_t launch_fused_n128(int fp16, const DivideParams& p, int n_patterns, hipStream_t s);
+hipError_t launch_fused_group_n32(int fp16, const Group<DivideParams>& g, int blocks, hipStream_t s);
+hipError_t launch_fused_group_n64(int fp16, const Group<DivideParams>& g, int blocks, hipStream_t s);
+hipError_t launch_fused_group_n128(int fp16, const Group<DivideParams>& g, int blocks, hipStream_t s);
 hipError_t launch_sp_n32(const DivideParams& p, int count, hipStream_t s);
 hipError_t launch_sp_n64(const DivideParams& p, int count, hipStream_t s);
 hipError_t launch_sp_n128(const DivideParams& p, int count, hipStream_t s);

@@ -3,14 +3,16 @@
 Requests (a scan plus an algorithm) arrive over time.  The server admits a
 request when a slot is free and its exact device workspace
 (`pty_workspace_bytes`) fits in the remaining HBM budget, keeps every admitted
-scan's state resident on the device, and advances all admitted scans together:
-each tick launches `chunk` iterations of every scan, interleaved across one
-HIP stream per scan (`pty_iterate_many`), so their kernels overlap on the
-device.  After each tick a scan whose Fourier error is below the tolerance, or
-that has run its iteration limit, completes: its object and probe are copied
-out, its workspace is released, and the next waiting request can take the
-slot.  The completion decision is taken only every `chunk` iterations, so a
-request's result does not depend on what else shares the GPU.
+scan's state resident on the device, and advances all admitted scans together
+on one stream: each tick runs up to `chunk` iterations of every scan through
+`pty_iterate_many`, whose grouped launches run each kernel once for up to
+eight scans of the same pattern size, so small scans share the GPU instead of
+queueing behind each other.  After a tick (one synchronisation for all scans)
+a scan whose Fourier error is below its tolerance, or that has run its
+iteration limit, completes: its object and probe are copied out, its
+workspace is released, and the next waiting request can take the slot.  The
+completion decision is taken only every `chunk` iterations, so a request's
+result does not depend on what else shares the GPU.
 
 All arithmetic runs in the HIP library; this module only schedules.
 """
@@ -113,16 +115,11 @@ class Server:
         self.chunk = int(chunk)
         self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
         self.clock = clock
-        self._free_streams: list = []
-
-    def _stream(self):
-        if self._free_streams:
-            return self._free_streams.pop()
-        return self.torch.cuda.Stream(device=self.device)   # default priority
+        self.stream = torch.cuda.Stream(device=self.device)   # all scans' work; default priority
 
     def _admit(self, req: Request, now: float) -> _Active:
         torch = self.torch
-        stream = self._stream()
+        stream = self.stream
         with torch.cuda.stream(stream):
             dev = self.device
             scan = Scan(torch.as_tensor(req.pos).to(dev, non_blocking=False),
@@ -138,7 +135,6 @@ class Server:
         prb = a.scan.probe().cpu().numpy()
         it = a.scan.iteration
         a.scan.close()
-        self._free_streams.append(a.stream)
         return Result(a.req.rid, obj, prb, it, ef, a.req.arrival, a.admitted, now,
                       a.req.n_pos * it)
 
@@ -178,13 +174,14 @@ class Server:
             n = min(min(self.chunk - it % self.chunk, a.req.max_iter - it) for a, it in zip(active, its))
             iterate_many([a.scan for a in active], n)
             stats.ticks += 1
+            self.stream.synchronize()                     # one wait for every scan of the tick
             still = []
             for a, it in zip(active, its):
                 it += n
                 if it % self.chunk != 0 and it < a.req.max_iter:
                     still.append(a)
                     continue
-                m = a.scan.metrics(allow_diverged=True)   # waits for this scan's stream only
+                m = a.scan.metrics(allow_diverged=True)   # already complete
                 ef = m["fourier_err"]
                 done = it >= a.req.max_iter or not np.isfinite(ef) or ef < a.req.tol
                 if done:

@@ -165,3 +165,70 @@ def test_iterate_many_matches_iterate():
                                tb.view(torch.int64) if tb.dtype == torch.complex64 else tb)
         a.close()
         b.close()
+
+
+def test_grouped_launches_match_iterate_bitwise():
+    """pty_iterate_many on scans that share a stream runs grouped launches (one
+    launch per kernel class for up to eight scans of one pattern size, storage
+    and prologue mode); every scan's state must equal that of pty_iterate on
+    it alone, bitwise.  The mix covers every grouping branch: N = 32 ... 256,
+    float32 and float16 storage, the blend and x forms, the prologue modes of
+    DC, SF, RAAR and the full metrics, a known probe, two concur sweeps, and ten
+    scans of one size (two chunks)."""
+    import torch
+    import paper_2311_11466_amd as pk
+    dev = torch.device("cuda", 0)
+    # (n, raster, step, algorithm, param, storage, full_metrics, blind, sweeps)
+    specs = ([(64, 3, 24, a, p, "fp32", False, True, 1) for a, p in
+              [("RAAR", 0.75), ("DC", 0.0), ("SF", 0.0), ("DR", 0.0), ("RRR", 0.5), ("AR", 0.0),
+               ("TLAMBDA", 0.5), ("RAAR", 0.9), ("DC", 0.0), ("RAAR", 0.6)]]
+             + [(32, 4, 12, "TLAMBDA", 0.5, "fp32", True, True, 1),
+                (128, 2, 40, "RAAR", 0.75, "fp32", False, True, 1),
+                (128, 2, 40, "DR", 0.0, "fp16", False, True, 1),
+                (128, 2, 40, "DC", 0.0, "fp32", True, False, 1),
+                (256, 2, 80, "RRR", 0.5, "fp32", False, True, 1),
+                (256, 2, 80, "AR", 0.0, "fp16", True, True, 1),
+                (64, 3, 24, "RAAR", 0.75, "fp16", False, True, 2)])
+    scans = []
+    for i, (n, ras, step, *_rest) in enumerate(specs):
+        scans.append(make_scan(small_config(f"g{i}", n, ras, step, jitter=1, photons=1e6, seed=300 + 7 * i)))
+    shared = torch.cuda.Stream()
+
+    def mk(sc, spec, stream):
+        n, ras, step, algo, prm, storage, full, blind, sweeps = spec
+        with torch.cuda.stream(stream):
+            g = pk.Scan(torch.as_tensor(sc.pos.astype(np.int32)).to(dev),
+                        torch.as_tensor(sc.intensity.astype(np.float32)).to(dev),
+                        torch.as_tensor(sc.obj0.astype(np.complex64)).to(dev),
+                        torch.as_tensor(sc.probe0.astype(np.complex64)).to(dev),
+                        storage=storage, full_metrics=full, blind=blind, stream=stream)
+        g.set_algorithm_named(algo, prm)
+        g.set_concur_sweeps(sweeps)
+        return g
+    print("case: grouped launches,", len(specs), "scans", flush=True)
+    many = [mk(sc, sp, shared) for sc, sp in zip(scans, specs)]
+    pk.iterate_many(many, 4)
+    # a change of algorithm in the middle (switches some scans' form and mode)
+    many[0].set_algorithm_named("DC")
+    many[11].set_algorithm_named("SF")
+    pk.iterate_many(many, 3)
+    shared.synchronize()
+    for i, (sc, sp) in enumerate(zip(scans, specs)):
+        alone = mk(sc, sp, torch.cuda.current_stream())
+        alone.iterate(4)
+        if i == 0:
+            alone.set_algorithm_named("DC")
+        if i == 11:
+            alone.set_algorithm_named("SF")
+        alone.iterate(3)
+        for name, ta, tb in zip("xyop", many[i].get_state(), alone.get_state()):
+            assert torch.equal(ta.view(torch.int64), tb.view(torch.int64)), (i, sp, name)
+        ha, hb = many[i].metric_history(), alone.metric_history()
+        assert len(ha) == len(hb) == 7
+        for ma, mb in zip(ha, hb):
+            for key in ("fourier_err", "consistency_err", "change"):
+                va, vb = ma[key], mb[key]
+                assert (np.isnan(va) and np.isnan(vb)) or va == vb, (i, key, va, vb)
+        alone.close()
+    for g in many:
+        g.close()
