@@ -63,7 +63,7 @@ def kernel_name(cls: str, n: int) -> str:
     return KERNEL_NAMES[cls]
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{workload}.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{workload}_{storage}.json")
 PROFILE_STEPS = 50       # iterations of the kernel-timing pass (at most)
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_11466_amd", "csrc", f)
@@ -179,14 +179,22 @@ def run_cpu_baseline(scan, abc, max_patterns: int, n_iter: int):
             "one_core": round(one, 2), "one_core_s": round(t1, 1)}
 
 
-def load_traffic(cls: str, workload: str):
-    path = TRAFFIC_FILE.format(kernel=cls, workload=workload)
+def traffic_run(args) -> dict:
+    """The settings that decide which kernel variant runs (its traffic)."""
+    return {"storage": args.storage, "algorithm": args.algorithm, "param": args.param, "metrics": args.metrics,
+            "concur_sweeps": args.concur_sweeps, "schedule": args.schedule}
+
+
+def load_traffic(cls: str, workload: str, run: dict):
+    path = TRAFFIC_FILE.format(kernel=cls, workload=workload, storage=run["storage"])
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
     if t.get("source_hash") != kernel_source_hash():
         return None      # the kernel changed since the counters were taken
+    if t.get("run") != run:
+        return None      # counters of another kernel variant
     return t.get("bytes_per_launch")
 
 
@@ -268,7 +276,7 @@ def measure(args, workload: str, steps: int, warmup: int):
         rec["algorithmic_bytes"] = nbytes
         rec["GBs"] = round(nbytes / (us * 1e-6) / 1e9, 1) if nbytes else None
         rec["frac"] = round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if nbytes else None
-    traffic = [load_traffic(c, cfg.name) for c in div]
+    traffic = [load_traffic(c, cfg.name, traffic_run(args)) for c in div]
     d_us, d_bytes = units["divide"]
     roofline = {"bound": "hbm", "achieved": round(d_bytes / (d_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(d_bytes / (d_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
@@ -515,7 +523,7 @@ def bench_compare(args):
     print(json.dumps(line), flush=True)
 
 
-def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int):
+def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, run: dict):
     """Turn two rocprofv3 --pmc counter CSVs into the traffic file bench.py reads.
 
     FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by the
@@ -557,15 +565,30 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int
         w = pick(write, kname)
         if f is None or w is None or f_scale is None or w_scale is None:
             continue
-        out = {"kernel": kname, "workload": workload, "source_hash": src_hash,
+        out = {"kernel": kname, "workload": workload, "run": run, "source_hash": src_hash,
                "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w,
                "copy_bytes": copy_bytes, "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
                "fetch_scale": f_scale, "write_scale": w_scale,
                "bytes_per_launch": round(f * 1024 * f_scale + w * 1024 * w_scale)}
-        path = TRAFFIC_FILE.format(kernel=cls, workload=workload)
+        path = TRAFFIC_FILE.format(kernel=cls, workload=workload, storage=run["storage"])
         with open(path, "w") as fh:
             json.dump(out, fh, indent=1)
         print("wrote", path, out)
+
+
+def summarize_ktrace(stats_csv: str, title: str, command: str):
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
+    out = [f"# Kernel trace: {title}", "", "Command (after `cd /tmp && export TMPDIR=/tmp`; `<repo>` is the repository root):",
+           "", "```", command, "```", "", "Durations from `kernel_stats.csv`:", "",
+           "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share |", "|---|---:|---:|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"] if len(r["Name"]) < 90 else r["Name"][:87] + "..."
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {100 * float(r['TotalDurationNs']) / total:.1f} % |")
+    print("\n".join(out))
 
 
 def main():
@@ -604,11 +627,17 @@ def main():
                     help="also run an elementwise add of known traffic (counter calibration)")
     ap.add_argument("--copy-probe-bytes", type=int, default=1 << 30)
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-ktrace", nargs=3, metavar=("STATS_CSV", "TITLE", "COMMAND"),
+                    help="print a markdown summary of a rocprofv3 kernel_stats.csv")
     args = ap.parse_args()
     if args.also == "none":
         args.also = None
+    if args.summarize_ktrace:
+        summarize_ktrace(*args.summarize_ktrace)
+        return
     if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, args.copy_probe_bytes)
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, args.copy_probe_bytes,
+                      traffic_run(args))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the whole scan runs on a single MI355X "

@@ -186,10 +186,9 @@ __device__ __forceinline__ void object_update_body(const ObjParams& p, const int
 // request), so it adds exactly zero.  Tile maxima and metric slices are per
 // work-group.
 constexpr int kGroupTiles = 4;
-#ifndef PTY_OBJ_RING
-#define PTY_OBJ_RING 2
-#endif
-constexpr int kObjRing = PTY_OBJ_RING;   // list entries in flight per wave
+// list entries in flight per wave (3 and 4 measured the same, 6 and 8 slower:
+// the loop waits on memory latency with the registers that two sets leave)
+constexpr int kObjRing = 2;
 
 template <class St, int N>
 __device__ __forceinline__ void object_lds_body(const ObjParams& p, const int blk_id, const int grid) {
