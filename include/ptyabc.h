@@ -108,10 +108,13 @@ typedef struct {
   double tau;                 /* division guard; 0 selects 1e-10                 */
 } pty_scan_desc;
 
-/* Metrics of one iteration k (from x_k):
+/* Metrics of one iteration k (from x_k), the quantities behind the error
+ * lines of the simulation figures (Figs. 7 and 8; the paper plots them
+ * without a formula, so these definitions are this library's reading):
  *   fourier_err     sum (|F x_k| - sqrt(I))^2 / sum I
  *   consistency_err sum |z - y|^2 / sum |y|^2,  y = P^c_D x_k, z = P_C y
- *   change          ||x_{k+1} - x_k|| / ||x_k||                              */
+ *   change          ||x_{k+1} - x_k|| / ||x_k||
+ * Sums run over all patterns and pixels, in float64.                        */
 typedef struct {
   int64_t iteration;
   double fourier_err;
@@ -245,13 +248,19 @@ pty_status pty_object_error_noalloc(const float *obj, int32_t obj_h, int32_t obj
 /* Wait for all queued work of the scan. */
 pty_status pty_synchronize(pty_scan *scan);
 
-/* Copy the current object ([H][W] complex, 2*H*W floats) or probe
- * ([N][N] complex, 2*N*N floats) into dst (host or device memory).
- * n_floats is dst's capacity in floats. */
+/* Copy the current object O ([H][W] complex, 2*H*W floats) or probe P
+ * ([N][N] complex, 2*N*N floats) into dst (host or device memory): the pair
+ * that the last concur step P_C formed (Introduction, the flow of the 'abc'
+ * method), or the initial pair before the first iteration.  n_floats is
+ * dst's capacity in floats; PTY_ERR_INVALID_ARG if it is too small.
+ * Synchronises the scan's stream.  The object and probe hold the values of
+ * a completed iteration only: a pending x update of the last step does not
+ * change them. */
 pty_status pty_get_object(pty_scan *scan, float *dst, size_t n_floats, int32_t dst_on_device);
 pty_status pty_get_probe(pty_scan *scan, float *dst, size_t n_floats, int32_t dst_on_device);
 
-/* Metrics of the last completed iteration.  PTY_ERR_BAD_STATE before the
+/* Metrics of the last completed iteration (the error-line quantities
+ * defined at pty_metrics).  PTY_ERR_BAD_STATE before the
  * first iteration; PTY_ERR_DIVERGED (with *out filled) if the Fourier error is
  * not finite or another metric is infinite.  A NaN consistency or change
  * error marks a metric that iteration did not form (blend form, sequential
