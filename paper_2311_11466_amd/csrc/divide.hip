@@ -183,6 +183,13 @@ __device__ __forceinline__ void rows256_inv_body(const DivideParams& p, const in
   });
 }
 
+// Column block of the column pass's work-group b (0..15 within its pattern).
+// The amplitudes of 16 columns are 64 bytes per row, half a cache line, which
+// blocks 2m and 2m + 1 share; work-group b runs on XCD b mod 8, so both go to
+// XCD m and the second read of a line hits that XCD's L2 (in plain order the
+// pass fetched every amplitude line twice).
+__device__ __forceinline__ int col_block(int b) { return 2 * (b & 7) + ((b >> 3) & 1); }
+
 // One scan: grid (16, patterns).  Grouped (the served form): a flat grid, 16
 // consecutive work-groups per pattern.
 template <class St>
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(256) void rows256_fwd_kernel(DivideParams p) {
   rows256_fwd_body<St>(p, int(blockIdx.x), int(blockIdx.y));
 }
 __global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
-  cols256_body(p, int(blockIdx.x), int(blockIdx.y));
+  cols256_body(p, col_block(int(blockIdx.x)), int(blockIdx.y));
 }
 template <class St>
 __global__ __launch_bounds__(256) void rows256_inv_kernel(DivideParams p) {
@@ -202,7 +209,7 @@ __global__ __launch_bounds__(256) void pass256_group_kernel(Group<DivideParams> 
   const int sc = group_scan(g, b);
   const int l = b - g.first[sc];
   if (STAGE == 0) rows256_fwd_body<St>(g.p[sc], l & 15, l >> 4);
-  if (STAGE == 1) cols256_body(g.p[sc], l & 15, l >> 4);
+  if (STAGE == 1) cols256_body(g.p[sc], col_block(l & 15), l >> 4);
   if (STAGE == 2) rows256_inv_body<St>(g.p[sc], l & 15, l >> 4);
 }
 
