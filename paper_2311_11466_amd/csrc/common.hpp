@@ -217,8 +217,9 @@ struct StoreF32 {
   }
   // the object step's exit-wave loads use the default policy: non-temporal
   // ones measured slower (N = 256: 722 vs 675 us) and leave the probe step's
-  // second read of y without the memory-side cache (N = 128: 37.8 vs 25.4 us)
-  __device__ __forceinline__ static float2 load_buf(__amdgpu_buffer_rsrc_t r, int byte_off, float /*inv*/) {
+  // second read of y without the memory-side cache (N = 128: 37.8 vs 25.4 us).
+  // The value as stored (no storage scale), through a buffer resource.
+  __device__ __forceinline__ static float2 load_buf_unscaled(__amdgpu_buffer_rsrc_t r, int byte_off) {
     return buffer_load_f2(r, byte_off);
   }
 };
@@ -252,12 +253,13 @@ struct StoreF16 {
       p[i] = h;
     }
   }
-  __device__ __forceinline__ static float2 load_buf(__amdgpu_buffer_rsrc_t r, int byte_off, float inv_scale) {
+  // the stored value times 2^s (the caller applies the power-of-two scale
+  // to its sums, which is exact)
+  __device__ __forceinline__ static float2 load_buf_unscaled(__amdgpu_buffer_rsrc_t r, int byte_off) {
     const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
     __half2 h;
     __builtin_memcpy(&h, &v, 4);
-    const float2 f = __half22float2(h);
-    return make_float2(f.x * inv_scale, f.y * inv_scale);
+    return __half22float2(h);
   }
 };
 

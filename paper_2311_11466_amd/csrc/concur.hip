@@ -115,6 +115,10 @@ __device__ __forceinline__ void object_update_body(const ObjParams& p, const int
   }
   pm = block_max<256>(pm, red);
   const double thr = p.tau * double(pm);
+  // the exit waves are summed as stored: float16 storage holds y 2^s, and
+  // scaling the float64 sums by 2^-s afterwards is exact (the same bits as
+  // scaling every load)
+  const double ysc = St::kFormat ? double(p.inv_scale) : 1.0;
 
   double nr[4] = {0, 0, 0, 0}, ni[4] = {0, 0, 0, 0}, dd[4] = {0, 0, 0, 0};
   const __amdgpu_buffer_rsrc_t prs = buffer_rsrc(p.probe, NN * 8);
@@ -126,12 +130,17 @@ __device__ __forceinline__ void object_update_body(const ObjParams& p, const int
     const int base = dr * N + du;
     const int j = __builtin_amdgcn_readfirstlane(en.x);       // one entry per wave
     const __amdgpu_buffer_rsrc_t yrs = buffer_rsrc(ys + size_t(j) * NN, NN * int(sizeof(elem)));
+    // byte offsets of the lane's pixel 0 (probe, exit wave), kOutside where
+    // its column is outside the window; a row outside the window needs no
+    // test: in unsigned arithmetic its offset is at or above N^2 elements
+    // (or, below row 0, at or above 2^31), outside the buffer, so it reads
+    // zero without a request like the out-of-window columns
+    const unsigned op = cin ? unsigned(base) * 8u : unsigned(kOutside);
+    const unsigned oy = cin ? unsigned(base) * unsigned(sizeof(elem)) : unsigned(kOutside);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const bool ok = cin && (unsigned)(dr + 4 * i) < (unsigned)N;
-      const int u = base + 4 * N * i;
-      pv[i] = buffer_load_f2(prs, ok ? u * 8 : kOutside);
-      yv[i] = St::load_buf(yrs, ok ? u * int(sizeof(elem)) : kOutside, p.inv_scale);
+      pv[i] = buffer_load_f2(prs, int(op + 32u * unsigned(N) * i));
+      yv[i] = St::load_buf_unscaled(yrs, int(oy + 4u * unsigned(N) * unsigned(sizeof(elem)) * i));
     }
   };
   auto accumulate = [&](const float2 (&pv)[4], const float2 (&yv)[4]) {
@@ -168,7 +177,7 @@ __device__ __forceinline__ void object_update_body(const ObjParams& p, const int
     if (row < p.H && col < p.W) {
       float2 o = oldo[i];
       if (dd[i] > thr) {
-        o = make_float2(float(nr[i] / dd[i]), float(ni[i] / dd[i]));
+        o = make_float2(float(nr[i] * ysc / dd[i]), float(ni[i] * ysc / dd[i]));
         p.obj[size_t(row) * p.W + col] = o;
       }
       m = fmaxf(m, cnorm(o));
@@ -258,6 +267,7 @@ __device__ __forceinline__ void object_lds_body(const ObjParams& p, const int bl
   }
   pm = block_max<1024>(pm, red);      // its barriers also publish pl and cnt
   const double thr = p.tau * double(pm);
+  const double ysc = St::kFormat ? double(p.inv_scale) : 1.0;   // as in object_update_body
   int maxlen = cnt[0];
 #pragma unroll
   for (int q = 1; q < kGroupTiles; ++q) maxlen = max(maxlen, cnt[q]);
@@ -268,17 +278,25 @@ __device__ __forceinline__ void object_lds_body(const ObjParams& p, const int bl
   auto issue = [&](int e, int cn, float2 (&pv)[4], float2 (&yv)[4]) {
     const int4 en = ent[g][min(e, cn - 1)];
     const int du = col - en.z;                 // column in the window
-    const int dr = row0 - en.y;                // row in the window of pixel 0
+    // row in the window of pixel 0: the same for the whole wave (one entry,
+    // one row0 per wave), so the row tests below are scalar
+    const int dr = __builtin_amdgcn_readfirstlane(row0 - en.y);
     const bool cin = e < cn && (unsigned)du < (unsigned)N;
     const int base = dr * N + du;
     const int j = __builtin_amdgcn_readfirstlane(en.x);       // one entry per wave
     const __amdgpu_buffer_rsrc_t yrs = buffer_rsrc(ys + size_t(j) * NN, NN * int(sizeof(elem)));
+    // exit-wave byte offset of the lane's pixel 0, kOutside where its column
+    // is outside the window; rows outside the window fall outside the buffer
+    // by themselves (unsigned offsets at or above N^2 elements, or at or
+    // above 2^31 below row 0) and read zero without a request.  The probe in
+    // LDS has no such check: its index takes the zero entry explicitly.
+    const unsigned oy = cin ? unsigned(base) * unsigned(sizeof(elem)) : unsigned(kOutside);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const bool ok = cin && (unsigned)(dr + 4 * i) < (unsigned)N;
       const int u = base + 4 * N * i;
       pv[i] = pl[ok ? u : kZero];
-      yv[i] = St::load_buf(yrs, ok ? u * int(sizeof(elem)) : kOutside, p.inv_scale);
+      yv[i] = St::load_buf_unscaled(yrs, int(oy + 4u * unsigned(N) * unsigned(sizeof(elem)) * i));
     }
   };
   auto accumulate = [&](const float2 (&pv)[4], const float2 (&yv)[4]) {
@@ -317,7 +335,7 @@ __device__ __forceinline__ void object_lds_body(const ObjParams& p, const int bl
     if (tile_ok && row < p.H && col < p.W) {
       float2 o = oldo[i];
       if (dd[i] > thr) {
-        o = make_float2(float(nr[i] / dd[i]), float(ni[i] / dd[i]));
+        o = make_float2(float(nr[i] * ysc / dd[i]), float(ni[i] * ysc / dd[i]));
         p.obj[size_t(row) * p.W + col] = o;
       }
       m = fmaxf(m, cnorm(o));
