@@ -424,8 +424,16 @@ def bench_sp(args):
     g = pk.Scan(torch.as_tensor(scan.pos).to(dev), torch.as_tensor(scan.intensity).to(dev),
                 torch.as_tensor(scan.obj0.astype(np.complex64)).to(dev),
                 torch.as_tensor(scan.probe0.astype(np.complex64)).to(dev), blind=True, device=dev)
-    from paper_2311_11466_amd.sp import disjoint_order
+    from paper_2311_11466_amd.sp import colour_classes, disjoint_order
     order = disjoint_order(scan.pos, cfg.n) if args.sp_order == "colour" else None
+    if args.sp_beta is None:
+        # the probe steps of a batch are summed: with beta = 1 a batch of b
+        # windows moves the probe b single steps at once, which diverges for
+        # the colour batches (the oracle's iteration as well); 1 / (mean batch
+        # size) makes a batch's summed step about one step.  The ascending
+        # order's batches hold a few windows: beta = 1.
+        n_col = int(colour_classes(scan.pos, cfg.n).max()) + 1
+        args.sp_beta = n_col / scan.n_pos if args.sp_order == "colour" else 1.0
     nb = 0
     for _ in range(args.warmup):
         nb = g.sp_iterate(order, args.sp_max_batch, args.sp_alpha, args.sp_beta)
@@ -446,8 +454,12 @@ def bench_sp(args):
     g.close()
     nn = cfg.n * cfg.n
     per_batch = scan.n_pos / max(nb, 1)
-    bytes_per = {"divide": 20 * nn * per_batch, "probe": 8 * nn * per_batch + 16 * nn}
-    names = {"divide": "divide_fused_kernel (sequential-projection mode)", "probe": "sp_probe_kernel"}
+    # per batch member pixel: sqrt(I) 4, object window read 8 and written 8,
+    # probe step written 8; the probe kernel reads the steps and the probe and
+    # writes the probe
+    bytes_per = {"divide": 28 * nn * per_batch, "probe": 8 * nn * per_batch + 16 * nn}
+    names = {"divide": ("sp256_rows_fwd_kernel + sp256_cols_kernel + sp256_rows_inv_kernel" if cfg.n == 256
+                        else "divide_fused_kernel (sequential-projection mode)"), "probe": "sp_probe_kernel"}
     kernels = {}
     for k, (ms, cnt) in prof.items():
         if cnt == 0:
@@ -607,7 +619,8 @@ def main():
     ap.add_argument("--sp-max-batch", type=int, default=0)
     ap.add_argument("--sp-order", default="colour", choices=["colour", "ascending"])
     ap.add_argument("--sp-alpha", type=float, default=1.0)
-    ap.add_argument("--sp-beta", type=float, default=1.0)
+    ap.add_argument("--sp-beta", type=float, default=None,
+                    help="SP probe step size (default: 1 / mean batch size for the colour order, else 1)")
     ap.add_argument("--concur-sweeps", type=int, default=1, help="(object, probe) sweeps per concur step")
     ap.add_argument("--schedule", default="constant", choices=["constant", "linear"],
                     help="linear: the preset parameter moves from --param to --param-end")

@@ -194,7 +194,9 @@ pty_status pty_shadow(pty_scan *scan, float *obj_out, float *probe_out);
 
 /* One iteration of sequential projections (Introduction: the constraint sets
  * visited one after another, in a fixed or shuffled order, with relaxed
- * projections), for N <= 128 (PTY_ERR_UNSUPPORTED otherwise).  The sets are
+ * projections), for every supported N (N = 256 runs each batch as the three
+ * passes of the divide: rows forward, columns with the modulus projection,
+ * rows inverse with the step).  The sets are
  * the per-position modulus sets; the step onto set j, with psi = P S_j O,
  * psi' its Fourier-modulus projection and d = psi' - psi, is
  *   O <- O + alpha S_j^T[conj(P) d] / max|P|^2

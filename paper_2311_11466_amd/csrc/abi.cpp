@@ -46,6 +46,7 @@ enum Mode { MODE_INIT = 0, MODE_MATERIAL = 1, MODE_PENDING = 2, MODE_PENDING_W =
 
 struct Layout {
   size_t amp, x, y, tmp, obj, probe, pos, tile_off, tile_list, part, met, met2, ring, tile_max, pmax, tw, flag, eval, sp_list,
+      sp_omax,
       total;
   int tiles_x, tiles_y, n_tiles, max_list, G, chunk, npb, nslot, cap;
   size_t elem_bytes;
@@ -113,6 +114,7 @@ Layout make_layout(const pty_scan_desc* d) {
   L.flag = take(64);
   L.eval = take(size_t(object_error_blocks((long long)H * W) + 1) * 4 * 8);   // object-error partial sums, result
   L.sp_list = take(J * 4);                            // batch member lists of sequential projections
+  L.sp_omax = d->n == 256 ? take(J * 16 * 4) : size_t(-1);   // N = 256 SP: row-block maxima of |S_j O|^2
   L.total = off;
   return L;
 }
@@ -980,7 +982,6 @@ pty_status pty_sp_iterate(pty_scan* scan, const int32_t* order, int32_t max_batc
   try {
     pty_status st = check_usable(scan);
     if (st != PTY_OK) return st;
-    if (scan->N > 128) return fail(PTY_ERR_UNSUPPORTED, "sequential projections are built for N <= 128");
     if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(PTY_ERR_INVALID_ARG, "alpha, beta must be finite");
     if (max_batch < 0) return fail(PTY_ERR_INVALID_ARG, "max_batch must be >= 0");
     const int J = scan->J, N = scan->N;
@@ -1021,6 +1022,7 @@ pty_status pty_sp_iterate(pty_scan* scan, const int32_t* order, int32_t max_batc
       p.sp_alpha = float(alpha);
       p.sp_beta = float(beta);
       p.sp_blind = blind;
+      p.sp_omax = N == 256 ? scan->at<float>(scan->L.sp_omax) : nullptr;
       SpProbeParams q{};
       q.probe = scan->at<float2>(scan->L.probe);
       q.contrib = p.contrib;

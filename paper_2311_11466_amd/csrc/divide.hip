@@ -66,16 +66,20 @@ __device__ __forceinline__ void tmp_store(float2* p, size_t i, float2 v) {
 }
 
 // rb: the work-group's block of 16 rows, jl: its pattern within the launch
-template <class St>
+// (SP: its slot in the batch of sequential projections, whose pattern is
+// batch[jl]; the prologue is psi = P S_j O, and the block's maximum of
+// |S_j O|^2 goes to sp_omax for the inverse row pass)
+template <class St, bool SP = false>
 __device__ __forceinline__ void rows256_fwd_body(const DivideParams& p, const int rb, const int jl) {
   __shared__ float2 lds[16 * LTH];
   __shared__ float2 twt[16 * 16];      // twt[16 a + b] = tw[a b]
   __shared__ double red[MF_COUNT * 4];
+  __shared__ float fred[4];
   const int tid = threadIdx.x;
   const int t = tid & 15, rl = tid >> 4;
   twt[tid] = p.tw[(tid >> 4) * (tid & 15)];
   const int r = rb * 16 + rl;
-  const int j = p.j_begin + jl;
+  const int j = SP ? p.batch[jl] : p.j_begin + jl;
   const size_t base = size_t(j) * L256 * L256;
   const int2 pj = p.pos[j];
   using elem = typename St::elem;
@@ -85,12 +89,19 @@ __device__ __forceinline__ void rows256_fwd_body(const DivideParams& p, const in
   double acc[MF_COUNT];
 #pragma unroll
   for (int q = 0; q < MF_COUNT; ++q) acc[q] = 0.0;
+  float om = 0.0f;                     // SP: max |S_j O|^2 of the thread's pixels
 
   // prologue: column c = t + 16 c1
   static_for<0, 16>([&](auto c1) {
     const int c = t + 16 * c1.value;
     const int idx = r * L256 + c;
-    const float2 z = cmul(p.probe[idx], p.obj[size_t(pj.x + r) * p.obj_w + (pj.y + c)]);
+    const float2 ov = p.obj[size_t(pj.x + r) * p.obj_w + (pj.y + c)];
+    const float2 z = cmul(p.probe[idx], ov);
+    if constexpr (SP) {
+      om = fmaxf(om, cnorm(ov));
+      v[c1.value] = z;
+      return;
+    }
     float2 xo = make_float2(0.f, 0.f), yo = make_float2(0.f, 0.f);
     if (p.read_x) xo = St::load(xs, base + idx, p.inv_scale);
     if (p.read_y) yo = St::load(ys, base + idx, p.inv_scale);
@@ -115,18 +126,23 @@ __device__ __forceinline__ void rows256_fwd_body(const DivideParams& p, const in
   dft_reg<16, false>(v);                                  // over c2 -> kc2; thread t = kc1
   static_for<0, 16>([&](auto k2) { tmp_store(p.tmp, base + r * L256 + t + 16 * k2.value, v[k2.value]); });
 
-  block_sum<MF_COUNT, 256>(acc, red);
+  if constexpr (SP) {
+    om = block_max<256>(om, fred);
+    if (tid == 0) p.sp_omax[jl * 16 + rb] = om;
+  }
+  block_sum<MF_COUNT, 256>(acc, red);   // SP: zeros (no consistency or change partials)
   if (tid >= MF_EC_NUM && tid < MF_COUNT)
     p.met[(size_t(j) * p.nslot + rb) * MF_COUNT + tid] = acc[tid];
 }
 
+template <bool SP = false>
 __device__ __forceinline__ void cols256_body(const DivideParams& p, const int cb, const int jl) {
   __shared__ float2 lds[16 * LT];
   __shared__ double red[2 * 4];
   const int tid = threadIdx.x;
   const int cl = tid & 15, t = tid >> 4;
   const int col = cb * 16 + cl;
-  const int j = p.j_begin + jl;
+  const int j = SP ? p.batch[jl] : p.j_begin + jl;
   const size_t base = size_t(j) * L256 * L256;
   float2 v[16];
   // rows r = t + 16 r1
@@ -158,15 +174,21 @@ __device__ __forceinline__ void cols256_body(const DivideParams& p, const int cb
   if (tid < 2) p.met[(size_t(j) * p.nslot + cb) * MF_COUNT + tid] = acc[tid];
 }
 
-template <class St>
+// SP: the epilogue is the step of a sequential projection instead of the
+// store of y (see the fused kernel): with psi = P S_j O formed again from the
+// window (no other member of the batch touches it) and d = P_D psi - psi, the
+// object window gets O + alpha conj(P) d / max|P|^2 and the batch slot's
+// probe step beta conj(S_j O) d / max|S_j O|^2 (blind).
+template <class St, bool SP = false>
 __device__ __forceinline__ void rows256_inv_body(const DivideParams& p, const int rb, const int jl) {
   __shared__ float2 lds[16 * LTH];
   __shared__ float2 twt[16 * 16];      // twt[16 a + b] = tw[a b]
+  __shared__ float fred[4];
   const int tid = threadIdx.x;
   const int t = tid & 15, rl = tid >> 4;
   twt[tid] = p.tw[(tid >> 4) * (tid & 15)];
   const int r = rb * 16 + rl;
-  const int j = p.j_begin + jl;
+  const int j = SP ? p.batch[jl] : p.j_begin + jl;
   const size_t base = size_t(j) * L256 * L256;
   using elem = typename St::elem;
   elem* __restrict__ ys = reinterpret_cast<elem*>(p.y);
@@ -178,9 +200,45 @@ __device__ __forceinline__ void rows256_inv_body(const DivideParams& p, const in
   __syncthreads();                                        // twt is complete
   static_for<1, 16>([&](auto k) { v[k.value] = cmulc(v[k.value], twt[16 * t + k.value]); });
   dft_reg<16, true>(v);                                   // over kc1 -> c1
+  if constexpr (SP) {
+    // step sizes alpha / max|P|^2 and beta / max|S_j O|^2 (zero where the
+    // maximum is zero); |P|^2 partial maxima: one per thread (npb <= 256)
+    float pm = tid < p.npb ? p.pmax_part[tid] : 0.0f;
+    float om = tid < 16 ? p.sp_omax[jl * 16 + tid] : 0.0f;
+    pm = block_max<256>(pm, fred);
+    om = block_max<256>(om, fred);
+    const float ka = pm > 0.f ? p.sp_alpha / pm : 0.f;
+    const float kb = om > 0.f ? p.sp_beta / om : 0.f;
+    const int2 pj = p.pos[j];
+    float2* __restrict__ orow = p.obj_out + size_t(pj.x + r) * p.obj_w + pj.y;
+    float2* __restrict__ crow = p.contrib + size_t(jl) * (L256 * L256) + r * L256;
+    static_for<0, 16>([&](auto c1) {
+      const int c = t + 16 * c1.value;
+      const float2 pp = p.probe[r * L256 + c];
+      const float2 oo = orow[c];
+      const float2 d = csub(v[c1.value], cmul(pp, oo));
+      const float2 po = cmulc(d, pp);                  // conj(P) d
+      orow[c] = make_float2(fmaf(ka, po.x, oo.x), fmaf(ka, po.y, oo.y));
+      if (p.sp_blind) {
+        const float2 oc = cmulc(d, oo);                // conj(S_j O) d
+        crow[c] = make_float2(kb * oc.x, kb * oc.y);
+      }
+    });
+    return;
+  }
   static_for<0, 16>([&](auto c1) {
     St::store(ys, base + r * L256 + t + 16 * c1.value, v[c1.value], p.scale);
   });
+}
+
+// Sequential projections at N = 256: the three passes for one batch, grid
+// (16, batch size); the pattern of slot s is batch[s].  The exit-wave storage
+// is not touched (the intermediate and the probe steps are float32).
+__global__ __launch_bounds__(256) void sp256_rows_fwd_kernel(DivideParams p) {
+  rows256_fwd_body<StoreF32, true>(p, int(blockIdx.x), int(blockIdx.y));
+}
+__global__ __launch_bounds__(256) void sp256_rows_inv_kernel(DivideParams p) {
+  rows256_inv_body<StoreF32, true>(p, int(blockIdx.x), int(blockIdx.y));
 }
 
 // Column block of the column pass's work-group b (0..15 within its pattern).
@@ -198,6 +256,9 @@ __global__ __launch_bounds__(256) void rows256_fwd_kernel(DivideParams p) {
 }
 __global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
   cols256_body(p, col_block(int(blockIdx.x)), int(blockIdx.y));
+}
+__global__ __launch_bounds__(256) void sp256_cols_kernel(DivideParams p) {
+  cols256_body<true>(p, col_block(int(blockIdx.x)), int(blockIdx.y));
 }
 template <class St>
 __global__ __launch_bounds__(256) void rows256_inv_kernel(DivideParams p) {
@@ -275,6 +336,13 @@ hipError_t launch_sp_batch(int n, const DivideParams& p, int count, hipStream_t 
     case 32: return launch_sp_n32(p, count, s);
     case 64: return launch_sp_n64(p, count, s);
     case 128: return launch_sp_n128(p, count, s);
+    case 256: {
+      const dim3 grid(16, count);
+      hipLaunchKernelGGL(sp256_rows_fwd_kernel, grid, dim3(256), 0, s, p);
+      hipLaunchKernelGGL(sp256_cols_kernel, grid, dim3(256), 0, s, p);
+      hipLaunchKernelGGL(sp256_rows_inv_kernel, grid, dim3(256), 0, s, p);
+      return hipGetLastError();
+    }
     default: return hipErrorInvalidValue;
   }
 }

@@ -51,6 +51,7 @@ struct DivideParams {
   int npb;
   float sp_alpha, sp_beta;
   int sp_blind;
+  float* sp_omax;           // N = 256: [batch slot][16] row-block maxima of |S_j O|^2
 };
 
 // Probe update after a batch of sequential projections: P += sum over the

@@ -13,9 +13,9 @@ from __future__ import annotations
 import numpy as np
 
 
-def disjoint_order(pos, n: int) -> np.ndarray:
-    """Positions sorted by a first-fit colouring of the window-overlap graph
-    (in ascending index order); within a colour, ascending index."""
+def colour_classes(pos, n: int) -> np.ndarray:
+    """First-fit colouring of the window-overlap graph in ascending index
+    order: positions of one colour have pairwise disjoint windows."""
     pos = np.asarray(pos, dtype=np.int64)
     j = len(pos)
     colour = np.full(j, -1, dtype=np.int64)
@@ -26,7 +26,14 @@ def disjoint_order(pos, n: int) -> np.ndarray:
         while c in used:
             c += 1
         colour[i] = c
-    return np.lexsort((np.arange(j), colour)).astype(np.int32)
+    return colour
+
+
+def disjoint_order(pos, n: int) -> np.ndarray:
+    """Positions sorted by colour class (colour_classes); within a colour,
+    ascending index.  The library runs each class as one batch."""
+    colour = colour_classes(pos, n)
+    return np.lexsort((np.arange(len(colour)), colour)).astype(np.int32)
 
 
 def shuffled_orders(n_pos: int, n_iter: int, seed: int) -> list:
@@ -35,4 +42,4 @@ def shuffled_orders(n_pos: int, n_iter: int, seed: int) -> list:
     return [rng.permutation(n_pos).astype(np.int32) for _ in range(n_iter)]
 
 
-__all__ = ["disjoint_order", "shuffled_orders"]
+__all__ = ["colour_classes", "disjoint_order", "shuffled_orders"]

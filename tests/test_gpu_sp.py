@@ -32,6 +32,9 @@ def get_scan(name):
             _SCANS[name] = make_scan(small_config("p128", 128, 4, 40, jitter=2, photons=1e6, seed=41))
         elif name == "p256":
             _SCANS[name] = make_scan(small_config("p256", 256, 3, 80, jitter=3, photons=1e5, seed=51))
+        elif name == "p256w":
+            # windows 352 apart are disjoint: batches of several patterns
+            _SCANS[name] = make_scan(small_config("p256w", 256, 4, 176, jitter=3, photons=1e5, seed=53))
         else:
             raise KeyError(name)
     return _SCANS[name]
@@ -85,6 +88,11 @@ def oracle_sp(scan, n_iter, orders, max_batch, alpha, beta, blind, seed=None, ep
     ("p128", 2, False, 0, 1.0, 0.7, True),
     ("p128", 2, True, 3, 0.9, 1.0, True),
     ("p64", 2, "colour", 0, 1.0, 1.0, True),
+    # N = 256: the three-pass form of the batch step
+    ("p256", 1, False, 0, 1.0, 1.0, True),
+    ("p256", 2, False, 0, 1.0, 1.0, False),
+    ("p256w", 2, True, 2, 0.9, 0.7, True),
+    ("p256w", 2, "colour", 0, 1.0, 1.0, True),
 ])
 def test_sp_matches_oracle(cfg, n_iter, shuffled, max_batch, alpha, beta, blind):
     scan = get_scan(cfg)
@@ -157,13 +165,20 @@ def test_sp_then_generalised_iteration():
     assert max(errs) <= 1e-5
 
 
-def test_sp_rejects_large_patterns_and_bad_orders():
+def test_sp_known_probe_batches_equal_sequential_n256():
+    """N = 256 (three passes per batch): with a known probe the batched
+    schedule equals the strictly sequential one."""
+    scan = get_scan("p256w")
+    say("case: SP N = 256 known probe, batched vs sequential")
+    a = gpu_sp(scan, 1, None, 0, 1.0, 1.0, False)
+    b = gpu_sp(scan, 1, None, 1, 1.0, 1.0, False)
+    assert a[3][0] < b[3][0] == scan.n_pos
+    assert rel_l2(a[0], b[0], covered_mask(scan)) <= 1e-6
+
+
+def test_sp_rejects_bad_orders():
     from paper_2311_11466_amd import PtyError
     say("case: SP argument checks")
-    g = gpu_scan(get_scan("p256"))
-    with pytest.raises(PtyError):
-        g.sp_iterate()
-    g.close()
     scan = get_scan("tiny_n32")
     g = gpu_scan(scan)
     bad = list(range(scan.n_pos))
