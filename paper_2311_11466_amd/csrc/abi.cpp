@@ -427,13 +427,33 @@ pty_status launch_iteration(pty_scan* s) {
 // pattern size and storage (and, for the divide, the same prologue mode)
 // instead of once per scan.  Each scan's kernels see exactly the parameters
 // of its own launch, so its results are bitwise those of pty_iterate.
+static pty_status launch_iteration_grouped_body(pty_scan* const* scans, int count, std::vector<IterPlan>& plans);
+
+// One iteration of every scan with grouped launches.  Once launches have
+// started, a failure leaves every scan of the call with device buffers that
+// its host state no longer describes, so all of them are marked failed.
 pty_status launch_iteration_grouped(pty_scan* const* scans, int count) {
   std::vector<IterPlan> plans(count);
   for (int i = 0; i < count; ++i) {
     const pty_status st = plan_iteration(scans[i], &plans[i]);
     if (st != PTY_OK) return st;
   }
+  const pty_status st = launch_iteration_grouped_body(scans, count, plans);
+  if (st != PTY_OK) {
+    for (int i = 0; i < count; ++i) scans[i]->failed = true;
+    return st;
+  }
+  for (int i = 0; i < count; ++i) commit_iteration(scans[i], plans[i]);
+  return PTY_OK;
+}
+
+static pty_status launch_iteration_grouped_body(pty_scan* const* scans, int count, std::vector<IterPlan>& plans) {
   const hipStream_t stream = scans[0]->stream;
+  // a failed grouped launch carried the work of every scan of its chunk
+  auto group_fail = [&](const int* m, int n, hipError_t e, const char* what) {
+    for (int q = 1; q < n; ++q) scans[m[q]]->failed = true;
+    return device_fail(scans[m[0]], e, what);
+  };
   // scans in call order, grouped by key; groups are launched in order of
   // their first scan, each in chunks of kGroupMax
   auto run_groups = [&](auto key_of, auto launch_chunk) -> pty_status {
@@ -471,7 +491,7 @@ pty_status launch_iteration_grouped(pty_scan* const* scans, int count) {
       int np[kGroupMax];
       for (int q = 0; q < n; ++q) { ps[q] = plans[m[q]].dp; np[q] = scans[m[q]]->J; }
       const hipError_t e = launch_divide_stage_group(s0->N, s0->fp16, ps, np, n, stage, stream);
-      return e == hipSuccess ? PTY_OK : device_fail(s0, e, "grouped divide launch");
+      return e == hipSuccess ? PTY_OK : group_fail(m, n, e, "grouped divide launch");
     });
     if (st != PTY_OK) return st;
   }
@@ -488,7 +508,7 @@ pty_status launch_iteration_grouped(pty_scan* const* scans, int count) {
       concur_params(scans[m[q]], plans[m[q]].mp, &os[q], &unused);
     }
     const hipError_t e = launch_object_update_group(s0->fp16, os, n, stream);
-    return e == hipSuccess ? PTY_OK : device_fail(s0, e, "grouped object launch");
+    return e == hipSuccess ? PTY_OK : group_fail(m, n, e, "grouped object launch");
   });
   if (st != PTY_OK) return st;
   st = run_groups([&](int i) { return (swept(i) || !plans[i].update_probe) ? -1 : scans[i]->N * 2 + scans[i]->fp16; },
@@ -500,7 +520,7 @@ pty_status launch_iteration_grouped(pty_scan* const* scans, int count) {
       concur_params(scans[m[q]], plans[m[q]].mp, &unused, &qs[q]);
     }
     const hipError_t e = launch_probe_partial_group(scans[m[0]]->fp16, qs, n, stream);
-    return e == hipSuccess ? PTY_OK : device_fail(scans[m[0]], e, "grouped probe launch");
+    return e == hipSuccess ? PTY_OK : group_fail(m, n, e, "grouped probe launch");
   });
   if (st != PTY_OK) return st;
   st = run_groups([&](int i) { return swept(i) ? -1 : 0; }, [&](const int* m, int n) -> pty_status {
@@ -512,11 +532,9 @@ pty_status launch_iteration_grouped(pty_scan* const* scans, int count) {
       up[q] = plans[m[q]].update_probe ? 1 : 0;
     }
     const hipError_t e = launch_probe_final_group(fs, up, n, stream);
-    return e == hipSuccess ? PTY_OK : device_fail(scans[m[0]], e, "grouped finalise launch");
+    return e == hipSuccess ? PTY_OK : group_fail(m, n, e, "grouped finalise launch");
   });
-  if (st != PTY_OK) return st;
-  for (int i = 0; i < count; ++i) commit_iteration(scans[i], plans[i]);
-  return PTY_OK;
+  return st;
 }
 
 // Finalise the metrics of iteration k-1 and/or materialise x_k.

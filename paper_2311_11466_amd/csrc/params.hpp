@@ -139,8 +139,12 @@ struct FlushParams {
 
 // Grouped launch: one launch runs the same kernel for up to kGroupMax scans
 // (same pattern size, storage and prologue mode); scan s owns the launch's
-// work-groups [first[s], first[s+1]), each block range a multiple of 8 so that
-// a block's XCD is the same as in a launch of its scan alone.
+// work-groups [first[s], first[s+1]).  Work-group b runs on XCD b mod 8.  The
+// object and probe launches pad each scan's range to a multiple of 8, so a
+// block's XCD (and xcd_block's mapping) is the one of its scan's launch alone;
+// the N = 256 passes take 16 blocks per pattern, so their pairing of column
+// blocks on one XCD holds too.  The fused divide's ranges are not padded: its
+// per-pattern work does not depend on where it runs.
 constexpr int kGroupMax = 8;
 template <class P>
 struct Group {
