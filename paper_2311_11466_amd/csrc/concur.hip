@@ -49,6 +49,9 @@ __device__ void metric_finish(const MetricParams& p, double* red) {
   double acc[MF_COUNT];
 #pragma unroll
   for (int q = 0; q < MF_COUNT; ++q) acc[q] = 0.0;
+  // (unrolled so that several slices' loads are in flight; the additions
+  // keep their order)
+#pragma unroll 8
   for (int i = threadIdx.x; i < p.slices; i += 256) {
 #pragma unroll
     for (int q = 0; q < MF_COUNT; ++q) acc[q] += p.part2[size_t(i) * MF_COUNT + q];
@@ -405,6 +408,7 @@ __device__ __forceinline__ void probe_final_body(const FinalParams& p, const int
   const int NN = p.N * p.N;
   const int u = b * 256 + threadIdx.x;
   float om = 0.0f;
+#pragma unroll 8
   for (int i = threadIdx.x; i < p.n_tiles; i += 256) om = fmaxf(om, p.tile_max[i]);
   om = block_max<256>(om, fred);
   const double thr = p.tau * double(om);
