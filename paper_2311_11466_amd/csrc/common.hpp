@@ -173,24 +173,8 @@ __device__ __forceinline__ float2 buffer_load_f2(__amdgpu_buffer_rsrc_t r, int b
 // form), float16 exit waves (half the bytes) are fastest with plain accesses.
 // load_stream is the load of the probe sums, the last reader in an iteration.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-#ifndef PTY_NT_STORE_F32
-#define PTY_NT_STORE_F32 1
-#endif
-#ifndef PTY_NT_STORE_F16
-#define PTY_NT_STORE_F16 0
-#endif
-#ifndef PTY_NT_LOAD_F32
-#define PTY_NT_LOAD_F32 1
-#endif
-#ifndef PTY_NT_LOAD_F16
-#define PTY_NT_LOAD_F16 0
-#endif
-#ifndef PTY_NT_PROBE_F32
-#define PTY_NT_PROBE_F32 1
-#endif
-#ifndef PTY_NT_PROBE_F16
-#define PTY_NT_PROBE_F16 0
-#endif
+constexpr bool kNtStoreF32 = true, kNtLoadF32 = true, kNtProbeF32 = true;
+constexpr bool kNtStoreF16 = false, kNtLoadF16 = false, kNtProbeF16 = false;
 
 struct StoreF32 {
   using elem = float2;
@@ -200,13 +184,13 @@ struct StoreF32 {
     return make_float2(v.x, v.y);
   }
   __device__ __forceinline__ static float2 load(const elem* p, size_t i, float /*inv_scale*/) {
-    return PTY_NT_LOAD_F32 ? load_nt(p, i) : p[i];
+    return kNtLoadF32 ? load_nt(p, i) : p[i];
   }
   __device__ __forceinline__ static float2 load_stream(const elem* p, size_t i, float /*inv_scale*/) {
-    return PTY_NT_PROBE_F32 ? load_nt(p, i) : p[i];
+    return kNtProbeF32 ? load_nt(p, i) : p[i];
   }
   __device__ __forceinline__ static void store(elem* p, size_t i, float2 v, float /*scale*/) {
-    if (PTY_NT_STORE_F32) {
+    if constexpr (kNtStoreF32) {
       f32x2 w;
       w.x = v.x;
       w.y = v.y;
@@ -235,17 +219,17 @@ struct StoreF16 {
     return make_float2(f.x * inv_scale, f.y * inv_scale);
   }
   __device__ __forceinline__ static float2 load(const elem* p, size_t i, float inv_scale) {
-    if (PTY_NT_LOAD_F16) return cvt(__builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p) + i), inv_scale);
+    if constexpr (kNtLoadF16) return cvt(__builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p) + i), inv_scale);
     const float2 f = __half22float2(p[i]);
     return make_float2(f.x * inv_scale, f.y * inv_scale);
   }
   __device__ __forceinline__ static float2 load_stream(const elem* p, size_t i, float inv_scale) {
-    if (PTY_NT_PROBE_F16) return cvt(__builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p) + i), inv_scale);
+    if constexpr (kNtProbeF16) return cvt(__builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p) + i), inv_scale);
     return load(p, i, inv_scale);
   }
   __device__ __forceinline__ static void store(elem* p, size_t i, float2 v, float scale) {
     const __half2 h = __float22half2_rn(make_float2(v.x * scale, v.y * scale));
-    if (PTY_NT_STORE_F16) {
+    if constexpr (kNtStoreF16) {
       unsigned u;
       __builtin_memcpy(&u, &h, 4);
       __builtin_nontemporal_store(u, reinterpret_cast<unsigned*>(p) + i);
@@ -303,11 +287,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
 // multiple of 8 (xcd_pad); logical ids beyond the real count exit at once.
 constexpr int kXcds = 8;
 __host__ __device__ constexpr int xcd_pad(int n) { return (n + kXcds - 1) / kXcds * kXcds; }
-#ifndef PTY_XCD_MAP
-#define PTY_XCD_MAP 1
-#endif
 __device__ __forceinline__ int xcd_block(int b, int padded) {
-  return PTY_XCD_MAP ? (b % kXcds) * (padded / kXcds) + b / kXcds : b;
+  return (b % kXcds) * (padded / kXcds) + b / kXcds;
 }
 
 template <int NT>

@@ -120,10 +120,9 @@ struct DivGeom {
   // projection commutes with the sign except where it sets the phase to zero.
   static constexpr int PB2 = (M / 2) * 16 + 16;   // B <-> C plane of one pass: entry (k % (M/2)) * 16 + kk
   static constexpr int LDS_SPLIT = (M / 2) * PA > M * PB2 ? (M / 2) * PA : M * PB2;
-#ifndef PTY_PROLOGUE_GROUP
-#define PTY_PROLOGUE_GROUP 8
-#endif
-  static constexpr int GP = PTY_PROLOGUE_GROUP;  // prologue elements whose loads are issued together
+  // prologue elements whose loads are issued together (4: the same time; 16:
+  // 29 registers spilled and 13 % slower)
+  static constexpr int GP = 8;
   static_assert(SA >= 1 && SB >= 1 && SA * 16 == E && SB * M == E, "geometry");
 };
 

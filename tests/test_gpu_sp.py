@@ -55,8 +55,8 @@ def orders_for(scan, n_iter, shuffled, seed=77):
     return [rng.permutation(scan.n_pos) for _ in range(n_iter)]
 
 
-def gpu_sp(scan, n_iter, orders, max_batch, alpha, beta, blind):
-    g = gpu_scan(scan, blind=blind)
+def gpu_sp(scan, n_iter, orders, max_batch, alpha, beta, blind, storage="fp32"):
+    g = gpu_scan(scan, blind=blind, storage=storage)
     nb = []
     for i in range(n_iter):
         nb.append(g.sp_iterate(None if orders is None else orders[i], max_batch, alpha, beta))
@@ -130,6 +130,23 @@ def test_sp_known_probe_batches_equal_sequential():
     b = gpu_sp(scan, 2, None, 1, 1.0, 1.0, False)
     assert a[3][0] < b[3][0] == scan.n_pos
     assert rel_l2(a[0], b[0], covered_mask(scan)) <= 1e-6
+
+
+@pytest.mark.parametrize("cfg", ["p128", "p256w"])
+def test_sp_independent_of_storage(cfg):
+    """SP never reads or writes the exit-wave storage format (psi, the
+    intermediate and the probe steps are float32); with float16 storage the
+    probe steps span the x and y buffers and, at N = 256, the intermediate
+    has its own buffer.  The results must be bitwise those of float32
+    storage."""
+    scan = get_scan(cfg)
+    order = orders_for(scan, 2, "colour")
+    say("case: SP", cfg, "float32 vs float16 storage")
+    a = gpu_sp(scan, 2, order, 0, 1.0, 0.5, True, storage="fp32")
+    b = gpu_sp(scan, 2, order, 0, 1.0, 0.5, True, storage="fp16")
+    assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
+    assert np.array_equal(a[1].view(np.uint32), b[1].view(np.uint32))
+    assert np.array_equal(a[2], b[2]) and a[3] == b[3]
 
 
 def test_colour_order_batches():
