@@ -162,8 +162,8 @@ __device__ __forceinline__ void object_update_body(const ObjParams& p, const int
     __syncthreads();
     // (The conditional request of entry e + 2 makes the compiler wait for
     // every load before the second accumulation; issuing it unconditionally,
-    // as the N <= 128 kernel does, measured slower here: 676 vs 664 us
-    // float32, 640 vs 523 us float16 on the 4096-pattern scan.)
+    // as the N <= 128 kernel does, measured slower here: 697 vs 675 us
+    // float32, 533 vs 516 us float16 on the 4096-pattern scan.)
     float2 pa[4], ya[4], pb[4], yb[4];
     issue(0, cn, pa, ya);
     for (int e = 0; e < cn; e += 2) {
