@@ -87,6 +87,7 @@ __global__ __launch_bounds__(256) void metric_slice_kernel(MetricParams p) {
 // zero without a memory request, so it adds exactly zero.  The next entry's
 // requests are in flight while the current one is accumulated.
 constexpr int kListChunk = 256;
+static_assert(kListChunk == 256, "a tile's 256 threads stage one list entry each");
 
 // blk, grid: the work-group's index and the (multiple of 8) work-group count
 // of its scan's launch
@@ -158,7 +159,7 @@ __device__ __forceinline__ void object_update_body(const ObjParams& p, const int
   for (int c0 = e0; c0 < e1; c0 += kListChunk) {
     const int cn = min(kListChunk, e1 - c0);
     __syncthreads();
-    for (int i = threadIdx.x; i < cn; i += 256) ent[i] = p.tile_ent[c0 + i];
+    if (int(threadIdx.x) < cn) ent[threadIdx.x] = p.tile_ent[c0 + threadIdx.x];   // one entry per thread
     __syncthreads();
     // (The conditional request of entry e + 2 makes the compiler wait for
     // every load before the second accumulation; issuing it unconditionally,
@@ -314,7 +315,7 @@ __device__ __forceinline__ void object_lds_body(const ObjParams& p, const int bl
   for (int c0 = 0; c0 < maxlen; c0 += kListChunk) {   // same trip count in every group
     const int cn = min(kListChunk, len - c0);
     __syncthreads();
-    for (int i = lt; i < cn; i += 256) ent[g][i] = p.tile_ent[e0 + c0 + i];
+    if (lt < cn) ent[g][lt] = p.tile_ent[e0 + c0 + lt];   // one entry per thread
     __syncthreads();
     if (cn <= 0) continue;
     // a ring of kObjRing register sets: the following entries' requests are
@@ -407,15 +408,12 @@ __device__ __forceinline__ void probe_final_body(const FinalParams& p, const int
   }
   const int NN = p.N * p.N;
   const int u = b * 256 + threadIdx.x;
-  float om = 0.0f;
-#pragma unroll 8
-  for (int i = threadIdx.x; i < p.n_tiles; i += 256) om = fmaxf(om, p.tile_max[i]);
-  om = block_max<256>(om, fred);
-  const double thr = p.tau * double(om);
-  float m = 0.0f;
+  // the chunk sums first (they do not depend on the object maximum), so their
+  // loads overlap those of the tile maxima and the block reduction
+  double nr = 0.0, ni = 0.0, dd = 0.0;
+  float2 pv = make_float2(0.f, 0.f);
   if (u < NN) {
     const size_t plane = size_t(p.G) * NN;
-    double nr = 0.0, ni = 0.0, dd = 0.0;
     int g = 0;
     for (; g + 4 <= p.G; g += 4) {
       double a[4], c[4], d[4];
@@ -439,7 +437,15 @@ __device__ __forceinline__ void probe_final_body(const FinalParams& p, const int
       ni += p.part[plane + o];
       dd += p.part[2 * plane + o];
     }
-    float2 pv = p.probe[u];
+    pv = p.probe[u];
+  }
+  float om = 0.0f;
+#pragma unroll 8
+  for (int i = threadIdx.x; i < p.n_tiles; i += 256) om = fmaxf(om, p.tile_max[i]);
+  om = block_max<256>(om, fred);
+  const double thr = p.tau * double(om);
+  float m = 0.0f;
+  if (u < NN) {
     if (dd > thr) {
       pv = make_float2(float(nr / dd), float(ni / dd));
       p.probe[u] = pv;
