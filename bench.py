@@ -23,10 +23,16 @@ algorithmic bytes: read x, y and sqrt(I), write x and y, 36 B per pattern
 pixel in float32; the whole iteration's fraction at 52 B per pattern pixel
 (blind) is given beside it.  `traffic` is the divide's measured HBM bytes per
 iteration from rocprofv3 FETCH_SIZE / WRITE_SIZE counters (profiles/), null
-if the kernel sources changed since they were taken.
+if the kernel sources or the run settings differ from those the counters were
+taken with.  The CPU baseline is the FP64 oracle on a bounded sample of the
+same workload, on one core and on 16 (one single-threaded copy per core).
 
   python bench.py [--steps K] [--warmup W] [--workload large_n256|scan_n128|tiny_n32|served|compare]
-  python bench.py --summarize-pmc FETCH_DIR WRITE_DIR   (writes the traffic files under profiles/)
+                  [--storage fp16] [--metrics fourier] [--method sp] [--also none]
+  python bench.py --workload X --storage S --summarize-pmc FETCH_DIR WRITE_DIR
+                  (writes the traffic files under profiles/)
+  python bench.py --summarize-ktrace STATS_CSV TITLE COMMAND
+                  (a markdown summary of a rocprofv3 kernel_stats.csv)
 """
 from __future__ import annotations
 
