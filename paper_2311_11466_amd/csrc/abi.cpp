@@ -478,7 +478,7 @@ static pty_status launch_iteration_grouped_body(pty_scan* const* scans, int coun
       const pty_scan* s = scans[i];
       if (stage >= divide_stages(s->N)) return -1;                 // no such stage for this scan
       if (!divide_groupable(s->N, plans[i].dp)) return -2 - i;     // alone
-      return ((s->N * 2 + s->fp16) * 64) + (s->N == 256 ? 0 : divide_mode(plans[i].dp));
+      return ((s->N * 2 + s->fp16) * 64) + divide_mode(plans[i].dp);   // one prologue mode per group
     };
     const pty_status st = run_groups(key, [&](const int* m, int n) -> pty_status {
       if (key(m[0]) == -1) return PTY_OK;

@@ -27,7 +27,7 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
 }
-__device__ __forceinline__ float cnorm(float2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ float cnorm(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
 
 // ---------------------------------------------------------------------------
 // compile-time cos / sin of 2*pi*k/L, from the Taylor series on [0, pi/2) and
@@ -86,9 +86,22 @@ __device__ __forceinline__ float2 twiddle_const(float2 d) {
   } else {
     constexpr float c = float(trig2pi(k, L, false));
     constexpr float s = float(trig2pi(k, L, true));
-    // W = c - i s (forward), c + i s (inverse)
-    if constexpr (!INV) return make_float2(d.x * c + d.y * s, d.y * c - d.x * s);
-    else return make_float2(d.x * c - d.y * s, d.y * c + d.x * s);
+    // W = c - i s (forward), c + i s (inverse); explicit fused multiply-adds
+    // (a sum of two products left to the compiler is contracted differently
+    // in different instantiations of one kernel, and their results would then
+    // differ in the last bit).  Where |c| = |s| (odd multiples of pi/4) both
+    // components share one product: three operations instead of four.
+    if constexpr (c == s) {
+      if constexpr (!INV) { const float m = d.y * c; return make_float2(fmaf(d.x, c, m), fmaf(-d.x, c, m)); }
+      else { const float m = d.x * c; return make_float2(fmaf(-d.y, c, m), fmaf(d.y, c, m)); }
+    } else if constexpr (c == -s) {
+      if constexpr (!INV) { const float m = d.x * c; return make_float2(fmaf(d.y, s, m), fmaf(d.y, c, m)); }
+      else { const float m = d.y * c; return make_float2(fmaf(d.x, c, m), fmaf(d.x, s, m)); }
+    } else if constexpr (!INV) {
+      return make_float2(fmaf(d.x, c, d.y * s), fmaf(d.y, c, -(d.x * s)));
+    } else {
+      return make_float2(fmaf(d.x, c, -(d.y * s)), fmaf(d.y, c, d.x * s));
+    }
   }
 }
 

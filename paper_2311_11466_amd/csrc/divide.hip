@@ -1,6 +1,10 @@
 // Divide step, N = 256 three-pass form, flush, amplitude preparation and the
 // dispatch to the fused kernels (divide_fused.hpp, one translation unit per
 // size).
+// No implicit contraction of a * b + c: the kernels of this file exist in
+// one instantiation per prologue mode, and each must round every value the
+// same way (the products that should fuse are written as fused multiply-adds).
+#pragma clang fp contract(off)
 #include <algorithm>
 
 #include "divide_fused.hpp"
@@ -14,9 +18,10 @@ namespace pty {
 // threads.  In the row passes a row's 16 threads are lanes of one wave, so
 // the transpose needs no work-group barrier; it runs in two halves through a
 // buffer of 8 values per thread, and the twiddles come from a 16 x 16 table
-// in LDS: the forward row pass is limited by how many work-groups a CU holds
-// (half as many made it 38 % slower), and the smaller LDS and register
-// footprint allows seven instead of four.  The column pass, whose 16 threads
+// in LDS.  The forward row pass is bound by the memory requests it keeps in
+// flight: its prologue issues eight elements' loads at a time (compile-time
+// buffer modes), which costs registers (four waves per SIMD) but moves more
+// bytes than seven waves each waiting on one element.  The column pass, whose 16 threads
 // of a column sit in four waves, exchanges all values at once (the same
 // halving measured 5 % slower there); it keeps its exchange tiles interleaved
 // by column ([a][b][column]), so a wave's 16 columns touch consecutive LDS
@@ -69,7 +74,12 @@ __device__ __forceinline__ void tmp_store(float2* p, size_t i, float2 v) {
 // (SP: its slot in the batch of sequential projections, whose pattern is
 // batch[jl]; the prologue is psi = P S_j O, and the block's maximum of
 // |S_j O|^2 goes to sp_omax for the inverse row pass)
-template <class St, bool SP = false>
+// MODE: the prologue's buffers and metrics as in the fused kernel (Pro<MODE>;
+// compile-time except PRO_FLAGS), so the loads of GP elements go out together:
+// with the buffers chosen by runtime tests every element's loads waited for
+// the previous element (at most 4 loads in flight per wave; 1613 -> 1517 us
+// float32, 1553 -> 1192 us float16 on the 4096-pattern scan, same bits).
+template <class St, int MODE, bool SP = false>
 __device__ __forceinline__ void rows256_fwd_body(const DivideParams& p, const int rb, const int jl) {
   __shared__ float2 lds[16 * LTH];
   __shared__ float2 twt[16 * 16];      // twt[16 a + b] = tw[a b]
@@ -91,33 +101,52 @@ __device__ __forceinline__ void rows256_fwd_body(const DivideParams& p, const in
   for (int q = 0; q < MF_COUNT; ++q) acc[q] = 0.0;
   float om = 0.0f;                     // SP: max |S_j O|^2 of the thread's pixels
 
-  // prologue: column c = t + 16 c1
-  static_for<0, 16>([&](auto c1) {
-    const int c = t + 16 * c1.value;
-    const int idx = r * L256 + c;
-    const float2 ov = p.obj[size_t(pj.x + r) * p.obj_w + (pj.y + c)];
-    const float2 z = cmul(p.probe[idx], ov);
-    if constexpr (SP) {
-      om = fmaxf(om, cnorm(ov));
-      v[c1.value] = z;
-      return;
+  // prologue: column c = t + 16 c1, GP elements' loads at a time
+  using PR = Pro<MODE>;
+  const bool rx = PR::rx(p), ry = PR::ry(p), wx = PR::wx(p), mec = PR::ec(p), mdx = PR::dx(p);
+  constexpr int GP = 8;
+  const float2* __restrict__ orow = p.obj + size_t(pj.x + r) * p.obj_w + pj.y;
+  static_for<0, 16, GP>([&](auto g0) {
+    float2 zp[GP], zo[GP], xo[GP], yo[GP];
+    static_for<0, GP>([&](auto q) {
+      const int c = t + 16 * (g0.value + q.value);
+      const int idx = r * L256 + c;
+      zp[q.value] = p.probe[idx];
+      zo[q.value] = orow[c];
+      xo[q.value] = rx ? St::load(xs, base + idx, p.inv_scale) : make_float2(0.f, 0.f);
+      yo[q.value] = ry ? St::load(ys, base + idx, p.inv_scale) : make_float2(0.f, 0.f);
+    });
+    static_for<0, GP>([&](auto q) {
+      constexpr int c1 = g0.value + q.value;
+      const int idx = r * L256 + t + 16 * c1;
+      const float2 z = cmul(zp[q.value], zo[q.value]);
+      if constexpr (SP) {
+        om = fmaxf(om, cnorm(zo[q.value]));
+        v[c1] = z;
+      } else {
+        const float2 xn = update_x(z, yo[q.value], xo[q.value], p.alpha, p.beta, p.gamma);
+        if (mec) {
+          const double dr = double(z.x) - double(yo[q.value].x), di = double(z.y) - double(yo[q.value].y);
+          acc[MF_EC_NUM] += fma(dr, dr, di * di);
+          acc[MF_EC_DEN] += fma(double(yo[q.value].x), double(yo[q.value].x), double(yo[q.value].y) * yo[q.value].y);
+        }
+        if (mdx) {
+          const double dr = double(xn.x) - double(xo[q.value].x), di = double(xn.y) - double(xo[q.value].y);
+          acc[MF_DX_NUM] += fma(dr, dr, di * di);
+          acc[MF_DX_DEN] += fma(double(xo[q.value].x), double(xo[q.value].x), double(xo[q.value].y) * xo[q.value].y);
+        }
+        if (wx) St::store(xs, base + idx, xn, p.scale);
+        v[c1] = xn;
+      }
+    });
+    // the group's metric terms are summed before the next group's loads:
+    // without this the compiler forms every element's float64 terms first and
+    // holds them (205 instead of 72 registers, two waves per SIMD)
+    if constexpr (!SP) {
+#pragma unroll
+      for (int q = 0; q < MF_COUNT; ++q) asm volatile("" : "+v"(acc[q]));
     }
-    float2 xo = make_float2(0.f, 0.f), yo = make_float2(0.f, 0.f);
-    if (p.read_x) xo = St::load(xs, base + idx, p.inv_scale);
-    if (p.read_y) yo = St::load(ys, base + idx, p.inv_scale);
-    const float2 xn = update_x(z, yo, xo, p.alpha, p.beta, p.gamma);
-    if (p.prev_ec) {
-      const double dr = double(z.x) - double(yo.x), di = double(z.y) - double(yo.y);
-      acc[MF_EC_NUM] += dr * dr + di * di;
-      acc[MF_EC_DEN] += double(yo.x) * yo.x + double(yo.y) * yo.y;
-    }
-    if (p.prev_dx) {
-      const double dr = double(xn.x) - double(xo.x), di = double(xn.y) - double(xo.y);
-      acc[MF_DX_NUM] += dr * dr + di * di;
-      acc[MF_DX_DEN] += double(xo.x) * xo.x + double(xo.y) * xo.y;
-    }
-    if (p.write_x) St::store(xs, base + idx, xn, p.scale);
-    v[c1.value] = xn;
+    __builtin_amdgcn_sched_barrier(0);
   });
   dft_reg<16, false>(v);                                  // over c1 -> kc1
   __syncthreads();                                        // twt is complete
@@ -235,7 +264,7 @@ __device__ __forceinline__ void rows256_inv_body(const DivideParams& p, const in
 // (16, batch size); the pattern of slot s is batch[s].  The exit-wave storage
 // is not touched (the intermediate and the probe steps are float32).
 __global__ __launch_bounds__(256) void sp256_rows_fwd_kernel(DivideParams p) {
-  rows256_fwd_body<StoreF32, true>(p, int(blockIdx.x), int(blockIdx.y));
+  rows256_fwd_body<StoreF32, PRO_Z, true>(p, int(blockIdx.x), int(blockIdx.y));
 }
 __global__ __launch_bounds__(256) void sp256_rows_inv_kernel(DivideParams p) {
   rows256_inv_body<StoreF32, true>(p, int(blockIdx.x), int(blockIdx.y));
@@ -250,9 +279,9 @@ __device__ __forceinline__ int col_block(int b) { return 2 * (b & 7) + ((b >> 3)
 
 // One scan: grid (16, patterns).  Grouped (the served form): a flat grid, 16
 // consecutive work-groups per pattern.
-template <class St>
+template <class St, int MODE>
 __global__ __launch_bounds__(256) void rows256_fwd_kernel(DivideParams p) {
-  rows256_fwd_body<St>(p, int(blockIdx.x), int(blockIdx.y));
+  rows256_fwd_body<St, MODE>(p, int(blockIdx.x), int(blockIdx.y));
 }
 __global__ __launch_bounds__(256) void cols256_kernel(DivideParams p) {
   cols256_body(p, col_block(int(blockIdx.x)), int(blockIdx.y));
@@ -264,14 +293,15 @@ template <class St>
 __global__ __launch_bounds__(256) void rows256_inv_kernel(DivideParams p) {
   rows256_inv_body<St>(p, int(blockIdx.x), int(blockIdx.y));
 }
-template <class St, int STAGE>
+// MODE: the prologue mode every scan of the group shares (stage 0 only)
+template <class St, int STAGE, int MODE = PRO_GENERAL>
 __global__ __launch_bounds__(256) void pass256_group_kernel(Group<DivideParams> g) {
   const int b = int(blockIdx.x);
   const int sc = group_scan(g, b);
   const int l = b - g.first[sc];
-  if (STAGE == 0) rows256_fwd_body<St>(g.p[sc], l & 15, l >> 4);
-  if (STAGE == 1) cols256_body(g.p[sc], col_block(l & 15), l >> 4);
-  if (STAGE == 2) rows256_inv_body<St>(g.p[sc], l & 15, l >> 4);
+  if constexpr (STAGE == 0) rows256_fwd_body<St, MODE>(g.p[sc], l & 15, l >> 4);
+  if constexpr (STAGE == 1) cols256_body(g.p[sc], col_block(l & 15), l >> 4);
+  if constexpr (STAGE == 2) rows256_inv_body<St>(g.p[sc], l & 15, l >> 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -299,12 +329,12 @@ __global__ __launch_bounds__(256) void flush_kernel(FlushParams p) {
     if (p.read_y) yo = St::load(ys, base + idx, p.inv_scale);
     const float2 xn = p.wform ? blend_x(z, xo, p.alpha) : update_x(z, yo, xo, p.alpha, p.beta, p.gamma);
     double dr = double(z.x) - double(yo.x), di = double(z.y) - double(yo.y);
-    acc[0] += dr * dr + di * di;
-    acc[1] += double(yo.x) * yo.x + double(yo.y) * yo.y;
+    acc[0] += fma(dr, dr, di * di);
+    acc[1] += fma(double(yo.x), double(yo.x), double(yo.y) * yo.y);
     dr = double(xn.x) - double(xo.x);
     di = double(xn.y) - double(xo.y);
-    acc[2] += dr * dr + di * di;
-    acc[3] += double(xo.x) * xo.x + double(xo.y) * xo.y;
+    acc[2] += fma(dr, dr, di * di);
+    acc[3] += fma(double(xo.x), double(xo.x), double(xo.y) * xo.y);
     if (p.write_x) St::store(xs, base + idx, xn, p.scale);
   }
   block_sum<4, 256>(acc, red);
@@ -412,12 +442,28 @@ hipError_t launch_flush(int fp16, const FlushParams& p, int J, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class St, int MODE>
+static void launch_256_fwd(const DivideParams& p, const dim3 grid, hipStream_t s) {
+  hipLaunchKernelGGL((rows256_fwd_kernel<St, MODE>), grid, dim3(256), 0, s, p);
+}
+
 template <class St>
 static hipError_t launch_256_stage(const DivideParams& p, int n_patterns, int stage, hipStream_t s) {
   if (p.wform) return hipErrorInvalidValue;   // the three-pass form keeps x
   const dim3 grid(16, n_patterns);
   switch (stage) {
-    case 0: hipLaunchKernelGGL((rows256_fwd_kernel<St>), grid, dim3(256), 0, s, p); break;
+    case 0:
+      switch (prologue_mode(p)) {
+        case PRO_GENERAL: launch_256_fwd<St, PRO_GENERAL>(p, grid, s); break;
+        case PRO_UPDATE: launch_256_fwd<St, PRO_UPDATE>(p, grid, s); break;
+        case PRO_MATERIAL: launch_256_fwd<St, PRO_MATERIAL>(p, grid, s); break;
+        case PRO_INIT: launch_256_fwd<St, PRO_INIT>(p, grid, s); break;
+        case PRO_Z: launch_256_fwd<St, PRO_Z>(p, grid, s); break;
+        case PRO_Y_EC: launch_256_fwd<St, PRO_Y_EC>(p, grid, s); break;
+        case PRO_Y: launch_256_fwd<St, PRO_Y>(p, grid, s); break;
+        default: launch_256_fwd<St, PRO_FLAGS>(p, grid, s); break;
+      }
+      break;
     case 1: hipLaunchKernelGGL(cols256_kernel, grid, dim3(256), 0, s, p); break;
     case 2: hipLaunchKernelGGL((rows256_inv_kernel<St>), grid, dim3(256), 0, s, p); break;
     default: return hipErrorInvalidValue;
@@ -425,11 +471,30 @@ static hipError_t launch_256_stage(const DivideParams& p, int n_patterns, int st
   return hipGetLastError();
 }
 
+template <class St, int MODE>
+static void launch_256_fwd_group(const Group<DivideParams>& g, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((pass256_group_kernel<St, 0, MODE>), dim3(blocks), dim3(256), 0, s, g);
+}
+
+// Grouped forward row passes exist for the compile-time modes of the
+// iteration's steady state and first step (every scan of g in the mode of
+// g.p[0]); others return hipErrorInvalidValue (the host launches such scans
+// one by one).
 template <class St>
 static hipError_t launch_256_stage_group(const Group<DivideParams>& g, int blocks, int stage, hipStream_t s) {
   if (g.p[0].wform) return hipErrorInvalidValue;
   switch (stage) {
-    case 0: hipLaunchKernelGGL((pass256_group_kernel<St, 0>), dim3(blocks), dim3(256), 0, s, g); break;
+    case 0:
+      switch (prologue_mode(g.p[0])) {
+        case PRO_GENERAL: launch_256_fwd_group<St, PRO_GENERAL>(g, blocks, s); break;
+        case PRO_UPDATE: launch_256_fwd_group<St, PRO_UPDATE>(g, blocks, s); break;
+        case PRO_INIT: launch_256_fwd_group<St, PRO_INIT>(g, blocks, s); break;
+        case PRO_Z: launch_256_fwd_group<St, PRO_Z>(g, blocks, s); break;
+        case PRO_Y_EC: launch_256_fwd_group<St, PRO_Y_EC>(g, blocks, s); break;
+        case PRO_Y: launch_256_fwd_group<St, PRO_Y>(g, blocks, s); break;
+        default: return hipErrorInvalidValue;
+      }
+      break;
     case 1: hipLaunchKernelGGL((pass256_group_kernel<St, 1>), dim3(blocks), dim3(256), 0, s, g); break;
     case 2: hipLaunchKernelGGL((pass256_group_kernel<St, 2>), dim3(blocks), dim3(256), 0, s, g); break;
     default: return hipErrorInvalidValue;
@@ -473,7 +538,7 @@ int divide_stages(int n) { return n == 256 ? 3 : 1; }
 int divide_mode(const DivideParams& p) { return prologue_mode(p); }
 
 bool divide_groupable(int n, const DivideParams& p) {
-  if (n == 256) return !p.wform;
+  if (n == 256 && p.wform) return false;
   switch (prologue_mode(p)) {
     case PRO_GENERAL: case PRO_UPDATE: case PRO_INIT: case PRO_W_PENDING: case PRO_W_ZERO:
     case PRO_Z: case PRO_Y_EC: case PRO_Y:

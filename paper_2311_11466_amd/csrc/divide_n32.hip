@@ -1,4 +1,5 @@
 // The fused divide for N = 32 (64 threads per pattern).
+#pragma clang fp contract(off)   // as in divide.hip: one rounding for every prologue mode
 #include "divide_fused.hpp"
 
 namespace pty {

@@ -36,8 +36,7 @@ __device__ __forceinline__ float2 fourier_op(float2 X, float A, float c, float o
   const float m2 = fmaf(X.x, X.x, X.y * X.y);
   const bool nz = m2 >= 1.17549435e-38f;
   const float r = __builtin_amdgcn_rsqf(nz ? m2 : 1.0f);
-  const float mag = nz ? m2 * r : 0.0f;
-  const float d = mag - A;
+  const float d = nz ? fmaf(m2, r, -A) : -A;            // |X| - A
   ef_num = fmaf(d, d, ef_num);
   ef_den = fmaf(A, A, ef_den);
   const float cA = c * A;
