@@ -76,6 +76,13 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run paper_2311_11466_amd.build.build() first")
+    # torch ships its own HIP runtime under the same sonames as ROCm's.  The
+    # library must bind to the runtime torch uses, so torch is imported and
+    # its GPU state initialised first; loaded before torch, the library's
+    # code objects register with ROCm's runtime and its HIP calls then find no
+    # device in a process where torch runs the GPU.
+    torch = _torch()
+    torch.cuda.is_available()
     L = ctypes.CDLL(path)
     P = ctypes.c_void_p
     L.pty_workspace_bytes.argtypes = [ctypes.POINTER(ScanDesc)]
