@@ -25,7 +25,11 @@ namespace pty {
 // of a column sit in four waves, exchanges all values at once (the same
 // halving measured 5 % slower there); it keeps its exchange tiles interleaved
 // by column ([a][b][column]), so a wave's 16 columns touch consecutive LDS
-// words rather than one bank.
+// words rather than one bank.  Its twiddles come from the same LDS table:
+// read from the global table they took 30 loads and about 30 registers per
+// thread (127 -> 97 VGPRs; 1030 -> 943 us on the 4096-pattern scan, same
+// bits).  Issuing the amplitude loads at the start instead of in the Fourier
+// step is slower with the table (969 us: 9 more registers).
 // ---------------------------------------------------------------------------
 constexpr int L256 = 256;
 constexpr int LP = 17;                 // padded pitch of an exchange tile
@@ -167,9 +171,11 @@ __device__ __forceinline__ void rows256_fwd_body(const DivideParams& p, const in
 template <bool SP = false>
 __device__ __forceinline__ void cols256_body(const DivideParams& p, const int cb, const int jl) {
   __shared__ float2 lds[16 * LT];
+  __shared__ float2 twt[16 * 16];      // twt[16 a + b] = tw[a b]
   __shared__ double red[2 * 4];
   const int tid = threadIdx.x;
   const int cl = tid & 15, t = tid >> 4;
+  twt[tid] = p.tw[(tid >> 4) * (tid & 15)];
   const int col = cb * 16 + cl;
   const int j = SP ? p.batch[jl] : p.j_begin + jl;
   const size_t base = size_t(j) * L256 * L256;
@@ -177,7 +183,8 @@ __device__ __forceinline__ void cols256_body(const DivideParams& p, const int cb
   // rows r = t + 16 r1
   static_for<0, 16>([&](auto r1) { v[r1.value] = tmp_load(p.tmp, base + (t + 16 * r1.value) * L256 + col); });
   dft_reg<16, false>(v);                                  // over r1 -> kr1
-  static_for<1, 16>([&](auto k) { v[k.value] = cmul(v[k.value], p.tw[t * k.value]); });
+  __syncthreads();                                        // twt is complete
+  static_for<1, 16>([&](auto k) { v[k.value] = cmul(v[k.value], twt[16 * t + k.value]); });
   static_for<0, 16>([&](auto k) { lds[(k.value * LP + t) * 16 + cl] = v[k.value]; });
   __syncthreads();
   static_for<0, 16>([&](auto r2) { v[r2.value] = lds[(t * LP + r2.value) * 16 + cl]; });
@@ -195,7 +202,7 @@ __device__ __forceinline__ void cols256_body(const DivideParams& p, const int cb
   static_for<0, 16>([&](auto r2) { lds[(t * LP + r2.value) * 16 + cl] = v[r2.value]; });
   __syncthreads();
   static_for<0, 16>([&](auto k) { v[k.value] = lds[(k.value * LP + t) * 16 + cl]; });  // thread t = r2
-  static_for<1, 16>([&](auto k) { v[k.value] = cmulc(v[k.value], p.tw[t * k.value]); });
+  static_for<1, 16>([&](auto k) { v[k.value] = cmulc(v[k.value], twt[16 * t + k.value]); });
   dft_reg<16, true>(v);                                   // over kr1 -> r1
   static_for<0, 16>([&](auto r1) { tmp_store(p.tmp, base + (t + 16 * r1.value) * L256 + col, v[r1.value]); });
 
