@@ -69,7 +69,10 @@ typedef enum {
   PTY_STORE_FP32 = 0, /* exit waves x, y kept as complex float32              */
   PTY_STORE_FP16 = 1  /* kept as complex float16 times a power-of-two scale;
                          transforms and projections still run in float32 and
-                         the overlap sums in float64                          */
+                         the overlap sums in float64.  The iterate x_k is its
+                         stored (rounded) value wherever it is formed, so
+                         pty_get_state / pty_set_state in between iterations
+                         leave the results unchanged, as with float32       */
 } pty_storage;
 
 /* Named algorithms (Introduction lists them; the paper gives (1,1,1) for

@@ -202,6 +202,11 @@ struct StoreF32 {
   __device__ __forceinline__ static float2 load_stream(const elem* p, size_t i, float /*inv_scale*/) {
     return kNtProbeF32 ? load_nt(p, i) : p[i];
   }
+  // a value in storage form and back (float32: itself), and the store of a
+  // value already in storage form
+  __device__ __forceinline__ static elem pack(float2 v, float /*scale*/) { return v; }
+  __device__ __forceinline__ static float2 unpack(elem e, float /*inv_scale*/) { return e; }
+  __device__ __forceinline__ static void store_packed(elem* p, size_t i, elem e) { store(p, i, e, 1.0f); }
   __device__ __forceinline__ static void store(elem* p, size_t i, float2 v, float /*scale*/) {
     if constexpr (kNtStoreF32) {
       f32x2 w;
@@ -240,8 +245,19 @@ struct StoreF16 {
     if constexpr (kNtProbeF16) return cvt(__builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p) + i), inv_scale);
     return load(p, i, inv_scale);
   }
+  // storage form: v 2^s rounded to float16; unpack(pack(v)) is what load
+  // returns after store (both factors are powers of two)
+  __device__ __forceinline__ static elem pack(float2 v, float scale) {
+    return __float22half2_rn(make_float2(v.x * scale, v.y * scale));
+  }
+  __device__ __forceinline__ static float2 unpack(elem h, float inv_scale) {
+    const float2 f = __half22float2(h);
+    return make_float2(f.x * inv_scale, f.y * inv_scale);
+  }
   __device__ __forceinline__ static void store(elem* p, size_t i, float2 v, float scale) {
-    const __half2 h = __float22half2_rn(make_float2(v.x * scale, v.y * scale));
+    store_packed(p, i, pack(v, scale));
+  }
+  __device__ __forceinline__ static void store_packed(elem* p, size_t i, elem h) {
     if constexpr (kNtStoreF16) {
       unsigned u;
       __builtin_memcpy(&u, &h, 4);

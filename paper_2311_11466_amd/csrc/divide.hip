@@ -128,7 +128,9 @@ __device__ __forceinline__ void rows256_fwd_body(const DivideParams& p, const in
         om = fmaxf(om, cnorm(zo[q.value]));
         v[c1] = z;
       } else {
-        const float2 xn = update_x(z, yo[q.value], xo[q.value], p.alpha, p.beta, p.gamma);
+        // x_k as the storage keeps it (float16: rounded; see the fused kernel)
+        const elem xe = St::pack(update_x(z, yo[q.value], xo[q.value], p.alpha, p.beta, p.gamma), p.scale);
+        const float2 xn = St::unpack(xe, p.inv_scale);
         if (mec) {
           const double dr = double(z.x) - double(yo[q.value].x), di = double(z.y) - double(yo[q.value].y);
           acc[MF_EC_NUM] += fma(dr, dr, di * di);
@@ -139,7 +141,7 @@ __device__ __forceinline__ void rows256_fwd_body(const DivideParams& p, const in
           acc[MF_DX_NUM] += fma(dr, dr, di * di);
           acc[MF_DX_DEN] += fma(double(xo[q.value].x), double(xo[q.value].x), double(xo[q.value].y) * xo[q.value].y);
         }
-        if (wx) St::store(xs, base + idx, xn, p.scale);
+        if (wx) St::store_packed(xs, base + idx, xe);
         v[c1] = xn;
       }
     });
@@ -334,7 +336,10 @@ __global__ __launch_bounds__(256) void flush_kernel(FlushParams p) {
     float2 xo = make_float2(0.f, 0.f), yo = make_float2(0.f, 0.f);
     if (p.read_x) xo = St::load(xs, base + idx, p.inv_scale);
     if (p.read_y) yo = St::load(ys, base + idx, p.inv_scale);
-    const float2 xn = p.wform ? blend_x(z, xo, p.alpha) : update_x(z, yo, xo, p.alpha, p.beta, p.gamma);
+    // x_k as the divide's prologue forms it (in storage form)
+    const elem xe = St::pack(p.wform ? blend_x(z, xo, p.alpha) : update_x(z, yo, xo, p.alpha, p.beta, p.gamma),
+                             p.scale);
+    const float2 xn = St::unpack(xe, p.inv_scale);
     double dr = double(z.x) - double(yo.x), di = double(z.y) - double(yo.y);
     acc[0] += fma(dr, dr, di * di);
     acc[1] += fma(double(yo.x), double(yo.x), double(yo.y) * yo.y);
@@ -342,7 +347,7 @@ __global__ __launch_bounds__(256) void flush_kernel(FlushParams p) {
     di = double(xn.y) - double(xo.y);
     acc[2] += fma(dr, dr, di * di);
     acc[3] += fma(double(xo.x), double(xo.x), double(xo.y) * xo.y);
-    if (p.write_x) St::store(xs, base + idx, xn, p.scale);
+    if (p.write_x) St::store_packed(xs, base + idx, xe);
   }
   block_sum<4, 256>(acc, red);
   for (int q = threadIdx.x; q < p.nslot * MF_COUNT; q += 256) {

@@ -192,8 +192,12 @@ __device__ __forceinline__ void divide_fused_body(const DivideParams& p, const i
         constexpr int r1 = e / 4, c1 = e % 4;
         const unsigned idx = (r2 + M * r1) * N + (c2 + M * c1);
         const float2 z = PR::gather ? cmul(zp[q.value], zo[q.value]) : make_float2(0.f, 0.f);
-        const float2 xn = PR::wf ? blend_x(z, xo[q.value], p.alpha)
+        // x_k as the storage keeps it (float16: rounded), so that a run
+        // that stores x_k and reads it back continues with the same bits
+        const float2 xf = PR::wf ? blend_x(z, xo[q.value], p.alpha)
                                  : update_x(z, yo[q.value], xo[q.value], p.alpha, p.beta, p.gamma);
+        const typename St::elem xe = St::pack(xf, p.scale);
+        const float2 xn = PR::sp ? xf : St::unpack(xe, p.inv_scale);
         if constexpr (PR::sp) om = fmaxf(om, cnorm(zo[q.value]));
         if (mec) {
           const float dr = z.x - yo[q.value].x, di = z.y - yo[q.value].y;
@@ -205,7 +209,7 @@ __device__ __forceinline__ void divide_fused_body(const DivideParams& p, const i
           dx_n = fmaf(dr, dr, fmaf(di, di, dx_n));
           dx_d = fmaf(xo[q.value].x, xo[q.value].x, fmaf(xo[q.value].y, xo[q.value].y, dx_d));
         }
-        if (wx) St::store(xb, idx, xn, p.scale);
+        if (wx) St::store_packed(xb, idx, xe);
         if constexpr (PR::wf) xk[s.value * 16 + e] = xn;
         v[s.value * 16 + e] = xn;
       });
