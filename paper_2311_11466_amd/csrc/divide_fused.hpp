@@ -120,9 +120,13 @@ struct DivGeom {
   // projection commutes with the sign except where it sets the phase to zero.
   static constexpr int PB2 = (M / 2) * 16 + 16;   // B <-> C plane of one pass: entry (k % (M/2)) * 16 + kk
   static constexpr int LDS_SPLIT = (M / 2) * PA > M * PB2 ? (M / 2) * PA : M * PB2;
-  // prologue elements whose loads are issued together (4: the same time; 16:
-  // 29 registers spilled and 13 % slower)
-  static constexpr int GP = 8;
+  // prologue elements whose loads are issued together: 4 (8 spilled 3
+  // registers in the float32 general mode and 7 in float16 once x_k is
+  // rounded to storage form; 4 spills none in the compile-time modes:
+  // 125 -> 123 us float32, 90.7 -> 84.6 us float16 on the 1024-pattern scan,
+  // same bits; 16 spilled 29 and was 13 % slower.  The rare runtime-flag
+  // form spills about 60 either way.)
+  static constexpr int GP = 4;
   static_assert(SA >= 1 && SB >= 1 && SA * 16 == E && SB * M == E, "geometry");
 };
 
@@ -197,6 +201,7 @@ __device__ __forceinline__ void divide_fused_body(const DivideParams& p, const i
         const float2 xf = PR::wf ? blend_x(z, xo[q.value], p.alpha)
                                  : update_x(z, yo[q.value], xo[q.value], p.alpha, p.beta, p.gamma);
         const typename St::elem xe = St::pack(xf, p.scale);
+        if (wx) St::store_packed(xb, idx, xe);
         const float2 xn = PR::sp ? xf : St::unpack(xe, p.inv_scale);
         if constexpr (PR::sp) om = fmaxf(om, cnorm(zo[q.value]));
         if (mec) {
@@ -209,7 +214,6 @@ __device__ __forceinline__ void divide_fused_body(const DivideParams& p, const i
           dx_n = fmaf(dr, dr, fmaf(di, di, dx_n));
           dx_d = fmaf(xo[q.value].x, xo[q.value].x, fmaf(xo[q.value].y, xo[q.value].y, dx_d));
         }
-        if (wx) St::store_packed(xb, idx, xe);
         if constexpr (PR::wf) xk[s.value * 16 + e] = xn;
         v[s.value * 16 + e] = xn;
       });
