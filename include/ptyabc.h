@@ -214,7 +214,11 @@ pty_status pty_shadow(pty_scan *scan, float *obj_out, float *probe_out);
  * batch schedule equals the sequential order.  The Fourier error of the exit
  * waves visited goes to the metric history (the other two metrics are NaN).
  * The generalised iteration's exit waves are discarded: a following
- * pty_iterate starts again from x = P S_j O. */
+ * pty_iterate starts again from x = P S_j O.  A batch sums its probe steps,
+ * so a batch of m windows moves the probe by up to m single steps: with
+ * batched orders beta of about 1 / (mean batch size) keeps the probe update
+ * stable (beta = 1 with batches of tens of windows diverges, in the FP64
+ * reference too); beta = 1 suits max_batch = 1. */
 pty_status pty_sp_iterate(pty_scan *scan, const int32_t *order, int32_t max_batch, double alpha, double beta);
 
 /* Number of batches of the last pty_sp_iterate call (-1 for NULL). */

@@ -245,7 +245,10 @@ class Scan:
         return o, p
 
     def sp_iterate(self, order=None, max_batch: int = 0, alpha: float = 1.0, beta: float = 1.0) -> int:
-        """One iteration of sequential projections; returns the number of batches."""
+        """One iteration of sequential projections (pty_sp_iterate); returns the
+        number of batches.  A batch sums the probe steps of its windows, so with
+        batched orders beta should be about 1 / (mean batch size), e.g.
+        beta = number of batches / n_pos; beta = 1 suits max_batch = 1."""
         if order is None:
             buf = None
         else:
