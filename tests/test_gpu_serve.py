@@ -173,8 +173,9 @@ def test_grouped_launches_match_iterate_bitwise():
     and prologue mode); every scan's state must equal that of pty_iterate on
     it alone, bitwise.  The mix covers every grouping branch: N = 32 ... 256,
     float32 and float16 storage, the blend and x forms, the prologue modes of
-    DC, SF, RAAR and the full metrics, a known probe, two concur sweeps, and ten
-    scans of one size (two chunks)."""
+    DC, SF, RAAR and the full metrics, a known probe, two concur sweeps, ten
+    scans of one size (two chunks), and scans whose state was read in between
+    (their next iteration starts from a materialised x)."""
     import torch
     import paper_2311_11466_amd as pk
     dev = torch.device("cuda", 0)
@@ -212,6 +213,12 @@ def test_grouped_launches_match_iterate_bitwise():
     many[0].set_algorithm_named("DC")
     many[11].set_algorithm_named("SF")
     pk.iterate_many(many, 3)
+    # reading the state materialises x: the next iteration of these scans runs
+    # the materialised-x prologue (alone at N = 256) beside grouped scans
+    read_mid = (11, 14, 15)
+    for i in read_mid:
+        many[i].get_state()
+    pk.iterate_many(many, 2)
     shared.synchronize()
     for i, (sc, sp) in enumerate(zip(scans, specs)):
         alone = mk(sc, sp, torch.cuda.current_stream())
@@ -221,10 +228,13 @@ def test_grouped_launches_match_iterate_bitwise():
         if i == 11:
             alone.set_algorithm_named("SF")
         alone.iterate(3)
+        if i in read_mid:
+            alone.get_state()
+        alone.iterate(2)
         for name, ta, tb in zip("xyop", many[i].get_state(), alone.get_state()):
             assert torch.equal(ta.view(torch.int64), tb.view(torch.int64)), (i, sp, name)
         ha, hb = many[i].metric_history(), alone.metric_history()
-        assert len(ha) == len(hb) == 7
+        assert len(ha) == len(hb) == 9
         for ma, mb in zip(ha, hb):
             for key in ("fourier_err", "consistency_err", "change"):
                 va, vb = ma[key], mb[key]
