@@ -204,3 +204,29 @@ def test_sp_rejects_bad_orders():
         g.sp_iterate(bad)
     assert g.iteration == 0
     g.close()
+
+
+@pytest.mark.parametrize("cfg", ["tiny_n32", "p128", "p256w"])
+def test_sp_resume_bitwise(cfg):
+    """Sequential projections keep only the object and probe: two iterations,
+    a checkpoint, a new scan that resumes for two more equals four
+    uninterrupted iterations bit for bit (colour and ascending orders)."""
+    from paper_2311_11466_amd.sp import colour_classes, disjoint_order
+    scan = get_scan(cfg)
+    say("case: SP resume", cfg)
+    order = disjoint_order(scan.pos, scan.n)
+    beta = float(colour_classes(scan.pos, scan.n).max() + 1) / scan.n_pos
+
+    def run(n, state=None):
+        g = gpu_scan(scan)
+        if state is not None:
+            g.set_state(*state)
+        for i in range(n):
+            g.sp_iterate(order if i % 2 == 0 else None, 0, 1.0, beta)
+        st = g.get_state()
+        g.close()
+        return st
+    ref = run(4)
+    got = run(2, state=run(2))
+    for name, r, q in zip("op", ref[2:], got[2:]):
+        assert np.array_equal(r.cpu().numpy().view(np.uint32), q.cpu().numpy().view(np.uint32)), name
