@@ -386,7 +386,7 @@ pty_status plan_iteration(pty_scan* s, IterPlan* L) {
   p.c = float(s->c);
   L->dp = p;
   L->update_probe = s->blind && s->k >= s->probe_update_start;
-  MetricParams mp = metric_params(s, object_blocks(s->N, s->L.n_tiles));
+  MetricParams mp = metric_params(s, metric_slices(s->N, s->L.n_tiles));
   mp.k_cur = s->k;
   mp.k_prev = (p.prev_ec || p.prev_dx) ? s->k - 1 : -1;
   mp.ec_ok = p.prev_ec;
@@ -956,7 +956,7 @@ pty_status pty_shadow(pty_scan* scan, float* obj_out, float* probe_out) {
     const size_t no = size_t(scan->H) * scan->W, np = size_t(scan->N) * scan->N;
     PTY_HIP(scan, hipMemcpyAsync(obj_out, O, no * 8, hipMemcpyDeviceToDevice, s), "shadow copy");
     PTY_HIP(scan, hipMemcpyAsync(probe_out, P, np * 8, hipMemcpyDeviceToDevice, s), "shadow copy");
-    MetricParams mp = metric_params(scan, object_blocks(scan->N, scan->L.n_tiles));   // writes no ring entry
+    MetricParams mp = metric_params(scan, metric_slices(scan->N, scan->L.n_tiles));   // writes no ring entry
     st = launch_concur(scan, mp, scan->blind && scan->k >= scan->probe_update_start, false);
     if (st != PTY_OK) return st;
     PTY_HIP(scan, launch_swap(O, reinterpret_cast<float2*>(obj_out), no, s), "shadow swap");

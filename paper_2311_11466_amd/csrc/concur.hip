@@ -113,7 +113,7 @@ __device__ __forceinline__ void object_update_body(const ObjParams& p, const int
   using elem = typename St::elem;
   const elem* ys = reinterpret_cast<const elem*>(p.y);
 
-  metric_slice<256>(p.mp, tile, mred);
+  if (tile < p.mp.slices) metric_slice<256>(p.mp, tile, mred);   // uniform in the work-group
   const int e0 = p.tile_off[tile], e1 = p.tile_off[tile + 1];
   float pm = 0.0f;
   for (int i = threadIdx.x; i < p.npb; i += 256) pm = fmaxf(pm, p.pmax_part[i]);
@@ -524,6 +524,16 @@ __global__ void convert_kernel(int to_store, const float2* src, typename St::ele
 // ---------------------------------------------------------------------------
 int object_blocks(int n, int n_tiles) {
   return n <= 128 ? (n_tiles + kGroupTiles - 1) / kGroupTiles : n_tiles;
+}
+
+// Metric slices: one per object work-group, at N = 256 at most
+// kMaxMetricSlices (its 16384 tiles at the 4096-pattern scan gave slices of
+// four entries, which the finalise block then added 64 after one another:
+// 24 us for the whole finalise launch).
+constexpr int kMaxMetricSlices = 256;
+int metric_slices(int n, int n_tiles) {
+  const int b = object_blocks(n, n_tiles);
+  return n <= 128 ? b : (b < kMaxMetricSlices ? b : kMaxMetricSlices);
 }
 
 template <class St>

@@ -177,8 +177,10 @@ int divide_mode(const DivideParams& p);
 bool divide_groupable(int n, const DivideParams& p);
 hipError_t launch_object_update(int fp16, const ObjParams& p, hipStream_t s);
 hipError_t launch_object_update_group(int fp16, const ObjParams* ps, int count, hipStream_t s);
-// work-groups of the object launch: each writes one tile_max entry and one metric slice
+// work-groups of the object launch: each writes one tile_max entry; the first
+// metric_slices of them also sum one metric slice each
 int object_blocks(int n, int n_tiles);
+int metric_slices(int n, int n_tiles);
 hipError_t launch_probe_partial(int fp16, const ProbeParams& p, hipStream_t s);
 hipError_t launch_probe_partial_group(int fp16, const ProbeParams* ps, int count, hipStream_t s);
 hipError_t launch_flush(int fp16, const FlushParams& p, int J, hipStream_t s);
