@@ -35,6 +35,9 @@ constexpr int L256 = 256;
 constexpr int LP = 17;                 // padded pitch of an exchange tile
 constexpr int LT = 16 * LP;            // one column's exchange tile (column pass)
 constexpr int LTH = 8 * LP;            // one row's half exchange tile (row passes)
+// Patterns per launch of a pass: the grid's second dimension holds the
+// pattern, and the device allows at most 65536 there.
+constexpr int kMaxPatternsPerLaunch = 65535;
 
 // Ordering of LDS accesses between the lanes of one wave: the hardware keeps
 // a wave's LDS operations in order, so only the compiler must not move them.
@@ -379,11 +382,21 @@ hipError_t launch_sp_batch(int n, const DivideParams& p, int count, hipStream_t 
     case 64: return launch_sp_n64(p, count, s);
     case 128: return launch_sp_n128(p, count, s);
     case 256: {
-      const dim3 grid(16, count);
-      hipLaunchKernelGGL(sp256_rows_fwd_kernel, grid, dim3(256), 0, s, p);
-      hipLaunchKernelGGL(sp256_cols_kernel, grid, dim3(256), 0, s, p);
-      hipLaunchKernelGGL(sp256_rows_inv_kernel, grid, dim3(256), 0, s, p);
-      return hipGetLastError();
+      // batch slots in launches of at most kMaxPatternsPerLaunch: a chunk's
+      // slot c reads batch[c0 + c] and its maxima and probe-step slots
+      for (int c0 = 0; c0 < count; c0 += kMaxPatternsPerLaunch) {
+        DivideParams q = p;
+        q.batch = p.batch + c0;
+        q.sp_omax = p.sp_omax + size_t(c0) * 16;
+        q.contrib = p.contrib + size_t(c0) * L256 * L256;
+        const dim3 grid(16, std::min(kMaxPatternsPerLaunch, count - c0));
+        hipLaunchKernelGGL(sp256_rows_fwd_kernel, grid, dim3(256), 0, s, q);
+        hipLaunchKernelGGL(sp256_cols_kernel, grid, dim3(256), 0, s, q);
+        hipLaunchKernelGGL(sp256_rows_inv_kernel, grid, dim3(256), 0, s, q);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
     }
     default: return hipErrorInvalidValue;
   }
@@ -460,8 +473,7 @@ static void launch_256_fwd(const DivideParams& p, const dim3 grid, hipStream_t s
 }
 
 template <class St>
-static hipError_t launch_256_stage(const DivideParams& p, int n_patterns, int stage, hipStream_t s) {
-  if (p.wform) return hipErrorInvalidValue;   // the three-pass form keeps x
+static hipError_t launch_256_chunk(const DivideParams& p, int n_patterns, int stage, hipStream_t s) {
   const dim3 grid(16, n_patterns);
   switch (stage) {
     case 0:
@@ -481,6 +493,21 @@ static hipError_t launch_256_stage(const DivideParams& p, int n_patterns, int st
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// One pass over all patterns, in launches of at most kMaxPatternsPerLaunch
+// (each takes its patterns from j_begin on; a pattern's work does not depend
+// on the launch it is in)
+template <class St>
+static hipError_t launch_256_stage(const DivideParams& p, int n_patterns, int stage, hipStream_t s) {
+  if (p.wform) return hipErrorInvalidValue;   // the three-pass form keeps x
+  for (int c0 = 0; c0 < n_patterns; c0 += kMaxPatternsPerLaunch) {
+    DivideParams q = p;
+    q.j_begin = p.j_begin + c0;
+    const hipError_t e = launch_256_chunk<St>(q, std::min(kMaxPatternsPerLaunch, n_patterns - c0), stage, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <class St, int MODE>
